@@ -1,0 +1,163 @@
+/*
+ * ddstress: stress of a site-dependent dislocation density on a rectangular
+ * grid of (possibly shape-anisotropic) cells, evaluated as the zero-padded FFT
+ * convolution of the density with precomputed interaction coefficients.
+ *
+ * Method: Berkov & Gorn, arXiv:1804.01830.
+ *   - Stress of a volume element and of the whole density: Sec. 2.1, Eq. (2),
+ *     Eq. (3a), Eq. (3b).
+ *   - Segment stress: Sec. 2.2, Eq. (6)-(7) (coordinate-free form).
+ *   - Interaction function f = sigma^AB / (Delta l b): Sec. 2.2, Eq. (9b).
+ *   - Discrete sum over cells and its FFT evaluation: Sec. 2.3, Eq. (10).
+ *   - Near-cell subdivision without multipole moments, zero self-term:
+ *     Sec. 2.3, Fig. 3.
+ *
+ * The computed quantity, for every cell r0 of the grid,
+ *     sigma_v(r0) = sum_{cells i} sum_{c < C} K_{v,c}(r0 - r_i) rho_c(r_i),
+ * is Eq. (10) summed over the dislocation types of Eq. (3b). Cell (i, j, k)
+ * has its centre at (i dx, j dy, k dz). The sample sits in an infinite
+ * medium: open boundaries, no periodic images.
+ *
+ * Density channels. A plan has L line directions t_l (1 <= L <= 3) and
+ * C = 3L density channels; channel c = 3 l + gamma holds the line density
+ * (dislocations per unit area, unit length^-2) of direction t_l multiplied by
+ * their Burgers component gamma (x, y, z), so rho_c has unit length^-1 and a
+ * Burgers vector that varies from cell to cell is folded into the channels.
+ *
+ * Stress output. Six components per cell in Voigt order
+ * (xx, yy, zz, yz, xz, xy), in the unit of mu.
+ *
+ * Array layouts (element type: float when precision == 32, double when 64):
+ *   rho:   [B][C][Nz][Ny][Nx]   x fastest, contiguous
+ *   sigma: [B][6][Nz][Ny][Nx]   x fastest, contiguous
+ *
+ * Streams are hipStream_t passed as void* (NULL = the null stream). Every
+ * call that takes a stream only enqueues work on it and returns; completion
+ * is observed through the stream. A plan is not thread-safe; distinct plans
+ * may run concurrently on distinct streams.
+ *
+ * Errors: every call returns a status and never throws. Argument and state
+ * errors are detected before anything is enqueued. A HIP error reported by
+ * the runtime while enqueueing is returned as DDSTRESS_E_DEVICE. The message
+ * of the last failing call on the calling thread is ddstress_last_error().
+ */
+#ifndef DDSTRESS_H
+#define DDSTRESS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddstress_plan_s* ddstress_plan;
+
+typedef enum {
+    DDSTRESS_OK = 0,
+    DDSTRESS_E_INVALID = 1,      /* bad argument or descriptor */
+    DDSTRESS_E_NOMEM = 2,        /* device allocation failed */
+    DDSTRESS_E_DEVICE = 3,       /* HIP runtime error */
+    DDSTRESS_E_STATE = 4,        /* call out of order (e.g. stress before set_density) */
+    DDSTRESS_E_UNSUPPORTED = 5   /* valid but not implemented (e.g. a size above the limits) */
+} ddstress_status;
+
+/* Where a buffer passed to set_density / stress lives. */
+typedef enum {
+    DDSTRESS_HOST = 0,           /* host memory: copied asynchronously on the stream */
+    DDSTRESS_DEVICE_COPY = 1,    /* device memory: copied into a plan-owned buffer */
+    DDSTRESS_DEVICE_BORROW = 2   /* device memory used in place by the next stress() calls;
+                                    the caller keeps it alive and unchanged until they complete */
+} ddstress_where;
+
+/* Problem statement: grid, cell sizes, elastic constants, line directions.
+ * Limits: 1 <= N_a <= 512 on every axis; 1 <= n_lines <= 3; batch >= 1. */
+typedef struct {
+    int32_t n[3];          /* Nx, Ny, Nz (x fastest in memory) */
+    double  d[3];          /* dx, dy, dz > 0, same length unit as 1/rho */
+    double  mu;            /* isotropic shear modulus > 0 */
+    double  nu;            /* Poisson ratio, -1 < nu < 0.5 */
+    int32_t n_lines;       /* L, 1..3; C = 3L channels */
+    double  t[3][3];       /* line directions t_l (normalised by the library; |t| = 0 is invalid) */
+    int32_t precision;     /* 32 or 64: arithmetic of the per-call FFTs and contraction.
+                              The interaction coefficients and their transform are always FP64. */
+    int32_t batch;         /* B >= 1 densities per stress() call sharing this plan */
+    int32_t near_shells;   /* S: a cell offset D is subdivided when |D_a| d_a <= S max(d) on every
+                              axis; 0 selects the default 2, negative is invalid */
+    uint32_t flags;        /* must be 0 */
+} ddstress_desc;
+
+/* Read-only facts about a plan. */
+typedef struct {
+    int32_t padded[3];     /* FFT lengths Px, Py, Pz: powers of two >= max(2, 2 N_a - 1) */
+    int32_t subdiv[3];     /* subcells per axis m_a = max(1, floor(d_a / min(d) + 1/2)) */
+    int32_t channels;      /* C = 3 L */
+    int32_t batch;         /* B */
+    int32_t precision;     /* 32 or 64 */
+    int32_t tile_z;        /* columns per block of the fused z kernel (fixes the spectrum layout) */
+    size_t  cached_bytes;  /* device bytes held for the plan's lifetime (kernel spectrum, tables) */
+    size_t  work_bytes;    /* device bytes of per-call work buffers */
+    double  kernel_real_max;  /* max |Re K^| over the spectrum: zero up to rounding (K is odd) */
+    double  kernel_imag_max;  /* max |Im K^| */
+} ddstress_info;
+
+/* Device bytes a plan for `desc` will hold: `cached_bytes` for its lifetime,
+ * `work_bytes` for its per-call buffers, `build_bytes` transiently during
+ * ddstress_plan_create. Any output pointer may be NULL. Synchronous, no
+ * device work. Returns DDSTRESS_E_INVALID for an invalid descriptor. */
+ddstress_status ddstress_plan_footprint(const ddstress_desc* desc, size_t* cached_bytes,
+                                        size_t* work_bytes, size_t* build_bytes);
+
+/* Build a plan: validates the descriptor, evaluates the interaction
+ * coefficients K_{v,c} on every cell offset in FP64 on the device (Eq. 6,
+ * Eq. 9b times the cell volume, near-cell subdivision, K(0) = 0), transforms
+ * them with an FP64 3D FFT and keeps the spectrum (purely imaginary because K
+ * is odd) in the plan precision. Work runs on `stream`; the call returns after
+ * the build has completed (it synchronises the stream). On success *out owns
+ * device memory until ddstress_plan_destroy. */
+ddstress_status ddstress_plan_create(const ddstress_desc* desc, void* stream, ddstress_plan* out);
+
+/* Hand the B densities [B][C][Nz][Ny][Nx] (plan precision) to the plan.
+ * HOST and DEVICE_COPY enqueue a copy on `stream` (the caller may reuse rho
+ * once the stream has passed that point; host memory should be pinned for the
+ * copy to be asynchronous); DEVICE_BORROW records the pointer only. */
+ddstress_status ddstress_set_density(ddstress_plan plan, const void* rho, int32_t where, void* stream);
+
+/* Enqueue the stress evaluation of the current densities on `stream`:
+ * forward x (real-to-complex), y and z transforms of the zero-padded density
+ * channels, the per-wavevector contraction with the kernel spectrum, inverse
+ * z, y and x (complex-to-real) transforms cropped to the grid.
+ * `sigma` is [B][6][Nz][Ny][Nx] in the plan precision; `where` is DDSTRESS_HOST
+ * (written through an internal device buffer and an asynchronous copy) or
+ * DDSTRESS_DEVICE_COPY / DDSTRESS_DEVICE_BORROW (both: written in place).
+ * DDSTRESS_E_STATE if no density was set. */
+ddstress_status ddstress_stress(ddstress_plan plan, void* sigma, int32_t where, void* stream);
+
+/* Facts about a plan (see ddstress_info). */
+ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info);
+
+/* Free a plan and its device memory (synchronises the device first). NULL is
+ * accepted. */
+ddstress_status ddstress_plan_destroy(ddstress_plan plan);
+
+/* The interaction coefficients of one line direction as the plan builds them
+ * (Sec. 2.3: Eq. 9b times the cell volume, near-cell subdivision, K(0) = 0),
+ * written in FP64 to the device buffer `out` laid out [3][6][Pz][Py][Px]
+ * (Burgers component gamma, Voigt component, then the padded grid in wrap
+ * order: index i on axis a holds offset i for i < N_a, i - P_a for
+ * i > P_a - N_a, and zero in between). `out` must hold 18 Px Py Pz doubles.
+ * Enqueued on `stream`. */
+ddstress_status ddstress_kernel_realspace(const ddstress_desc* desc, int32_t line, double* out,
+                                          void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ddstress_last_error(void);
+
+/* Library version string. */
+const char* ddstress_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDSTRESS_H */

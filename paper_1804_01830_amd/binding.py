@@ -1,0 +1,188 @@
+"""ctypes binding of ``libddstress.so`` (declared in ``include/ddstress.h``).
+
+Argument marshalling only: every step of the stress evaluation runs in the HIP
+library. Device memory and streams come from PyTorch (ROCm); the library
+receives raw device pointers and a ``hipStream_t``. There is no CPU fallback:
+if the library is missing or cannot be loaded, ``load()`` raises.
+"""
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libddstress.so")
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = range(6)
+HOST, DEVICE_COPY, DEVICE_BORROW = 0, 1, 2
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STATE", 5: "E_UNSUPPORTED"}
+
+# names exported by the library, in header order
+EXPORTS = ("ddstress_plan_footprint", "ddstress_plan_create", "ddstress_set_density", "ddstress_stress",
+           "ddstress_plan_get_info", "ddstress_plan_destroy", "ddstress_kernel_realspace",
+           "ddstress_last_error", "ddstress_version")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("d", ctypes.c_double * 3), ("mu", ctypes.c_double),
+                ("nu", ctypes.c_double), ("n_lines", ctypes.c_int32), ("t", (ctypes.c_double * 3) * 3),
+                ("precision", ctypes.c_int32), ("batch", ctypes.c_int32), ("near_shells", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("padded", ctypes.c_int32 * 3), ("subdiv", ctypes.c_int32 * 3), ("channels", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("precision", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+                ("cached_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t),
+                ("kernel_real_max", ctypes.c_double), ("kernel_imag_max", ctypes.c_double)]
+
+
+class DDStressError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load the library once and declare the signatures. Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run python -m paper_1804_01830_amd.build)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    S = ctypes.c_size_t
+    lib.ddstress_plan_footprint.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(S), ctypes.POINTER(S),
+                                            ctypes.POINTER(S)]
+    lib.ddstress_plan_create.argtypes = [ctypes.POINTER(Desc), P, ctypes.POINTER(P)]
+    lib.ddstress_set_density.argtypes = [P, P, ctypes.c_int32, P]
+    lib.ddstress_stress.argtypes = [P, P, ctypes.c_int32, P]
+    lib.ddstress_plan_get_info.argtypes = [P, ctypes.POINTER(Info)]
+    lib.ddstress_plan_destroy.argtypes = [P]
+    lib.ddstress_kernel_realspace.argtypes = [ctypes.POINTER(Desc), ctypes.c_int32, P, P]
+    for name in ("ddstress_plan_footprint", "ddstress_plan_create", "ddstress_set_density", "ddstress_stress",
+                 "ddstress_plan_get_info", "ddstress_plan_destroy", "ddstress_kernel_realspace"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.ddstress_last_error.restype = ctypes.c_char_p
+    lib.ddstress_last_error.argtypes = []
+    lib.ddstress_version.restype = ctypes.c_char_p
+    lib.ddstress_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def check(status):
+    if status != OK:
+        raise DDStressError(status, load().ddstress_last_error().decode())
+
+
+def make_desc(n, d, mu, nu, lines, precision=32, batch=1, near_shells=0, flags=0):
+    desc = Desc()
+    for a in range(3):
+        desc.n[a] = int(n[a])
+        desc.d[a] = float(d[a])
+    desc.mu = float(mu)
+    desc.nu = float(nu)
+    lines = [list(map(float, t)) for t in lines]
+    desc.n_lines = len(lines)
+    for l, t in enumerate(lines[:3]):
+        for a in range(3):
+            desc.t[l][a] = t[a]
+    desc.precision = int(precision)
+    desc.batch = int(batch)
+    desc.near_shells = int(near_shells)
+    desc.flags = int(flags)
+    return desc
+
+
+def footprint(desc):
+    c, w, b = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    check(load().ddstress_plan_footprint(ctypes.byref(desc), ctypes.byref(c), ctypes.byref(w), ctypes.byref(b)))
+    return c.value, w.value, b.value
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+class Plan:
+    """Owns one ``ddstress_plan``. Tensors are torch CUDA tensors of the plan
+    precision; ``stream`` is a torch stream (default: the current stream)."""
+
+    def __init__(self, desc, stream=None):
+        self.desc = desc
+        self._h = ctypes.c_void_p()
+        check(load().ddstress_plan_create(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(self._h)))
+        self.n = tuple(desc.n)
+        self.channels = 3 * desc.n_lines
+        self.batch = desc.batch
+        self.precision = desc.precision
+
+    def info(self):
+        info = Info()
+        check(load().ddstress_plan_get_info(self._h, ctypes.byref(info)))
+        return info
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_density(self, rho, where=DEVICE_BORROW, stream=None):
+        self._check_tensor(rho, (self.batch, self.channels))
+        self._rho_ref = rho           # keeps a borrowed buffer alive
+        check(load().ddstress_set_density(self._h, ctypes.c_void_p(rho.data_ptr()), where,
+                                          _stream_handle(stream)))
+
+    def stress(self, sigma, stream=None):
+        self._check_tensor(sigma, (self.batch, 6))
+        check(load().ddstress_stress(self._h, ctypes.c_void_p(sigma.data_ptr()), DEVICE_BORROW,
+                                     _stream_handle(stream)))
+        return sigma
+
+    def new_output(self):
+        import torch
+        dt = torch.float32 if self.precision == 32 else torch.float64
+        nx, ny, nz = self.n
+        return torch.empty((self.batch, 6, nz, ny, nx), dtype=dt, device="cuda")
+
+    def _check_tensor(self, t, lead):
+        import torch
+        dt = torch.float32 if self.precision == 32 else torch.float64
+        nx, ny, nz = self.n
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or tuple(t.shape) != (*lead, nz, ny, nx):
+            raise ValueError(f"expected a contiguous CUDA {dt} tensor of shape {(*lead, nz, ny, nx)}, "
+                             f"got {tuple(t.shape)} {t.dtype} on {t.device}")
+
+    def close(self):
+        if self._h:
+            check(load().ddstress_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def kernel_realspace(desc, line, out, stream=None):
+    """FP64 interaction coefficients of one line direction into the CUDA
+    tensor ``out`` of shape (3, 6, Pz, Py, Px) (see the header)."""
+    check(load().ddstress_kernel_realspace(ctypes.byref(desc), int(line), ctypes.c_void_p(out.data_ptr()),
+                                           _stream_handle(stream)))
+    return out
+
+
+def padded_lengths(n):
+    out = []
+    for v in n:
+        p = 1
+        while p < 2 * v - 1:
+            p *= 2
+        out.append(max(2, p))
+    return tuple(out)

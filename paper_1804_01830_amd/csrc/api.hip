@@ -1,0 +1,430 @@
+// C entry points: plan construction, density hand-over and the stress call.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ddstress_internal.hpp"
+
+namespace dds {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+[[noreturn]] void fail(ddstress_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(e == hipErrorOutOfMemory ? DDSTRESS_E_NOMEM : DDSTRESS_E_DEVICE,
+             std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+namespace {
+
+template <class F>
+ddstress_status guarded(F&& f) {
+    try {
+        f();
+        return DDSTRESS_OK;
+    } catch (const Error& e) {
+        g_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return DDSTRESS_E_NOMEM;
+    } catch (...) {
+        g_last_error = "unexpected internal error";
+        return DDSTRESS_E_DEVICE;
+    }
+}
+
+// Device buffer that frees itself.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t n, const char* what) {
+        release();
+        if (n == 0) n = 256;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(DDSTRESS_E_NOMEM, std::string("device allocation failed: ") + what + " (" +
+                                       std::to_string(n) + " bytes)");
+        }
+        bytes = n;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Shape facts derived from a descriptor.
+struct Shape {
+    int N[3];        // grid
+    int P[3];        // padded FFT lengths
+    int M, M1;       // x half length and non-redundant columns (M + 1)
+    int64_t wx;      // row stride of x spectra (complex elements)
+    int C, B, L;
+    int elem;        // bytes per real
+    int tkz, ntz;    // fused z tile and number of kx tiles
+    int64_t cells() const { return (int64_t)N[0] * N[1] * N[2]; }
+    int64_t padded() const { return (int64_t)P[0] * P[1] * P[2]; }
+};
+
+void validate(const ddstress_desc* d) {
+    if (!d) fail(DDSTRESS_E_INVALID, "descriptor is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (d->n[a] < 1) fail(DDSTRESS_E_INVALID, "grid sizes must be >= 1");
+        if (!(d->d[a] > 0.0) || !std::isfinite(d->d[a])) fail(DDSTRESS_E_INVALID, "cell sizes must be finite and > 0");
+    }
+    for (int a = 0; a < 3; ++a)
+        if (d->n[a] > kMaxLen / 2) fail(DDSTRESS_E_UNSUPPORTED, "grid sizes above 512 per axis are not supported");
+    if (!(d->mu > 0.0) || !std::isfinite(d->mu)) fail(DDSTRESS_E_INVALID, "mu must be finite and > 0");
+    if (!(d->nu > -1.0 && d->nu < 0.5)) fail(DDSTRESS_E_INVALID, "nu must lie in (-1, 0.5)");
+    if (d->n_lines < 1 || d->n_lines > 3) fail(DDSTRESS_E_INVALID, "n_lines must be 1, 2 or 3");
+    for (int l = 0; l < d->n_lines; ++l) {
+        const double n2 = d->t[l][0] * d->t[l][0] + d->t[l][1] * d->t[l][1] + d->t[l][2] * d->t[l][2];
+        if (!(n2 > 0.0) || !std::isfinite(n2)) fail(DDSTRESS_E_INVALID, "line directions must be finite and nonzero");
+    }
+    if (d->precision != 32 && d->precision != 64) fail(DDSTRESS_E_INVALID, "precision must be 32 or 64");
+    if (d->batch < 1) fail(DDSTRESS_E_INVALID, "batch must be >= 1");
+    if (d->near_shells < 0) fail(DDSTRESS_E_INVALID, "near_shells must be >= 0");
+    if (d->flags != 0) fail(DDSTRESS_E_UNSUPPORTED, "flags must be 0");
+}
+
+Shape make_shape(const ddstress_desc* d) {
+    Shape s{};
+    for (int a = 0; a < 3; ++a) {
+        s.N[a] = d->n[a];
+        s.P[a] = std::max(2, next_pow2(2 * d->n[a] - 1));
+    }
+    s.M = s.P[0] / 2;
+    s.M1 = s.M + 1;
+    s.wx = round_up(s.M1, 16);
+    s.L = d->n_lines;
+    s.C = 3 * d->n_lines;
+    s.B = d->batch;
+    s.elem = d->precision == 32 ? 4 : 8;
+    s.tkz = default_z_tk(s.P[2], s.elem);
+    s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
+    return s;
+}
+
+size_t spec_bytes(const Shape& s) {
+    return (size_t)s.P[1] * s.ntz * s.C * 6 * (size_t)s.P[2] * s.tkz * s.elem;
+}
+size_t twiddle_bytes(const Shape& s) { return (size_t)kTwiddleEntries * 2 * s.elem; }
+// complex elements of the two ping-pong work buffers
+int64_t work1_elems(const Shape& s) {
+    const int64_t a = (int64_t)s.B * s.C * s.N[2] * s.N[1] * s.wx;
+    const int64_t b = (int64_t)s.B * 6 * s.N[2] * s.P[1] * s.wx;
+    return std::max(a, b);
+}
+int64_t work2_elems(const Shape& s) {
+    const int64_t a = (int64_t)s.B * s.C * s.N[2] * s.P[1] * s.wx;
+    const int64_t b = (int64_t)s.B * 6 * s.N[2] * s.N[1] * s.wx;
+    return std::max(a, b);
+}
+size_t density_bytes(const Shape& s) { return (size_t)s.B * s.C * s.cells() * s.elem; }
+size_t sigma_bytes(const Shape& s) { return (size_t)s.B * 6 * s.cells() * s.elem; }
+size_t build_real_bytes(const Shape& s) { return (size_t)18 * s.padded() * sizeof(double); }
+size_t build_cplx_bytes(const Shape& s) {
+    return (size_t)18 * s.P[2] * s.P[1] * (size_t)s.wx * sizeof(cplx<double>);
+}
+
+}  // namespace
+}  // namespace dds
+
+using namespace dds;
+
+struct ddstress_plan_s {
+    ddstress_desc desc;
+    Shape shape;
+    DevBuf spec;        // kernel spectrum, plan precision
+    DevBuf tw;          // twiddles, plan precision
+    DevBuf work1, work2;
+    DevBuf rho_own;     // density copy (HOST / DEVICE_COPY)
+    DevBuf sigma_tmp;   // stress staging for HOST output
+    const void* rho = nullptr;
+    bool have_density = false;
+    int rows_x = 1, tk_y = 1;
+    double re_max = 0.0, im_max = 0.0;
+};
+
+namespace {
+
+template <typename T>
+void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
+    const Shape& s = p->shape;
+    DevBuf kr, kc, tw64, maxbits;
+    kr.alloc(build_real_bytes(s), "kernel coefficients");
+    kc.alloc(build_cplx_bytes(s), "kernel transform");
+    tw64.alloc((size_t)kTwiddleEntries * sizeof(cplx<double>), "FP64 twiddles");
+    maxbits.alloc(2 * sizeof(unsigned long long), "spectrum check");
+    std::vector<cplx<double>> host(kTwiddleEntries);
+    fill_twiddles<double>(host.data());
+    check_hip(hipMemcpyAsync(tw64.p, host.data(), host.size() * sizeof(cplx<double>), hipMemcpyHostToDevice, st),
+              "twiddle upload");
+    check_hip(hipMemsetAsync(maxbits.p, 0, 2 * sizeof(unsigned long long), st), "clear spectrum check");
+    const cplx<double>* tw = tw64.as<cplx<double>>();
+    const int64_t plane_r = s.padded();
+    const int64_t plane_c = (int64_t)s.P[2] * s.P[1] * s.wx;
+    const int rows = default_rows(s.M, 8);
+    const int tky = default_col_tk(s.P[1], 8);
+    const int tkz = default_col_tk(s.P[2], 8);
+    const double inv_p = 1.0 / (double)plane_r;
+    for (int l = 0; l < s.L; ++l) {
+        KernelParams kp = make_kernel_params(p->desc, l, s.P);
+        launch_kernel_build(kp, kr.as<double>(), st);
+        // x: 18 * Pz * Py rows of Px reals (no padding: the coefficients fill the grid)
+        launch_x_r2c<double>(s.M, kr.as<double>(), kc.as<cplx<double>>(), 18LL * s.P[2] * s.P[1], s.P[0],
+                             s.P[0], s.wx, tw, rows, st);
+        ColGeom gy{};
+        gy.ncols = s.M1;
+        gy.n_in = s.P[1];
+        gy.n_out = s.P[1];
+        gy.nouter = 1;
+        gy.nplanes = 18LL * s.P[2];
+        gy.irs = gy.ors = s.wx;
+        gy.ios = gy.oos = 0;
+        gy.ips = gy.ops = (int64_t)s.P[1] * s.wx;
+        launch_col_fft<double>(s.P[1], true, kc.as<cplx<double>>(), kc.as<cplx<double>>(), gy, tw, tky, st);
+        ColGeom gz{};
+        gz.ncols = s.M1;
+        gz.n_in = s.P[2];
+        gz.n_out = s.P[2];
+        gz.nouter = s.P[1];
+        gz.nplanes = 18;
+        gz.irs = gz.ors = (int64_t)s.P[1] * s.wx;
+        gz.ios = gz.oos = s.wx;
+        gz.ips = gz.ops = plane_c;
+        launch_col_fft<double>(s.P[2], true, kc.as<cplx<double>>(), kc.as<cplx<double>>(), gz, tw, tkz, st);
+        launch_extract<T>(kc.as<cplx<double>>(), p->spec.as<T>(), l, s.C, s.M1, s.wx, s.P[1], s.P[2], s.tkz,
+                          s.ntz, inv_p, maxbits.as<unsigned long long>(), st);
+    }
+    unsigned long long bits[2] = {0, 0};
+    check_hip(hipMemcpyAsync(bits, maxbits.p, sizeof(bits), hipMemcpyDeviceToHost, st), "spectrum check readback");
+    check_hip(hipStreamSynchronize(st), "plan build");
+    double re, im;
+    std::memcpy(&re, &bits[0], sizeof(double));
+    std::memcpy(&im, &bits[1], sizeof(double));
+    p->re_max = re;
+    p->im_max = im;
+}
+
+template <typename T>
+void upload_twiddles(ddstress_plan_s* p, hipStream_t st) {
+    std::vector<cplx<T>> host(kTwiddleEntries);
+    fill_twiddles<T>(host.data());
+    check_hip(hipMemcpyAsync(p->tw.p, host.data(), host.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, st),
+              "twiddle upload");
+    check_hip(hipStreamSynchronize(st), "twiddle upload");
+}
+
+template <typename T>
+void run_stress(ddstress_plan_s* p, T* sigma, hipStream_t st) {
+    const Shape& s = p->shape;
+    const T* rho = static_cast<const T*>(p->rho);
+    cplx<T>* w1 = p->work1.as<cplx<T>>();
+    cplx<T>* w2 = p->work2.as<cplx<T>>();
+    const cplx<T>* tw = p->tw.as<cplx<T>>();
+    const int64_t BC = (int64_t)s.B * s.C;
+    const int64_t B6 = (int64_t)s.B * 6;
+    const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2], Py = s.P[1];
+    // x forward: rows (b, c, z, y) of Nx reals -> M+1 complex
+    launch_x_r2c<T>(s.M, rho, w1, BC * Nz * Ny, Nx, Nx, s.wx, tw, p->rows_x, st);
+    // y forward: Ny rows -> Py rows
+    ColGeom gy{};
+    gy.ncols = s.M1;
+    gy.n_in = Ny;
+    gy.n_out = Py;
+    gy.nouter = 1;
+    gy.nplanes = BC * Nz;
+    gy.irs = s.wx;
+    gy.ips = (int64_t)Ny * s.wx;
+    gy.ors = s.wx;
+    gy.ops = (int64_t)Py * s.wx;
+    launch_col_fft<T>(Py, true, w1, w2, gy, tw, p->tk_y, st);
+    // z forward + contraction + z inverse
+    ZGeom gz{};
+    gz.ncols = s.M1;
+    gz.ntiles = s.ntz;
+    gz.nky = Py;
+    gz.nz = Nz;
+    gz.C = s.C;
+    gz.B = s.B;
+    gz.irs = (int64_t)Py * s.wx;
+    gz.iqs = (int64_t)Nz * Py * s.wx;
+    gz.ios = s.wx;
+    gz.ors = gz.irs;
+    gz.oqs = gz.iqs;
+    gz.oos = gz.ios;
+    launch_z_fused<T>(s.P[2], w2, w1, p->spec.as<T>(), gz, tw, s.tkz, st);
+    // y inverse: Py rows -> Ny rows
+    ColGeom gi{};
+    gi.ncols = s.M1;
+    gi.n_in = Py;
+    gi.n_out = Ny;
+    gi.nouter = 1;
+    gi.nplanes = B6 * Nz;
+    gi.irs = s.wx;
+    gi.ips = (int64_t)Py * s.wx;
+    gi.ors = s.wx;
+    gi.ops = (int64_t)Ny * s.wx;
+    launch_col_fft<T>(Py, false, w1, w2, gi, tw, p->tk_y, st);
+    // x inverse: rows (b, v, z, y) -> Nx reals
+    launch_x_c2r<T>(s.M, w2, sigma, B6 * Nz * Ny, Nx, s.wx, Nx, tw, p->rows_x, st);
+}
+
+void create_plan(const ddstress_desc* desc, hipStream_t st, ddstress_plan* out) {
+    if (!out) fail(DDSTRESS_E_INVALID, "output plan pointer is NULL");
+    *out = nullptr;
+    validate(desc);
+    auto* p = new ddstress_plan_s();
+    try {
+        p->desc = *desc;
+        p->shape = make_shape(desc);
+        const Shape& s = p->shape;
+        p->rows_x = default_rows(s.M, s.elem);
+        p->tk_y = default_col_tk(s.P[1], s.elem);
+        p->spec.alloc(spec_bytes(s), "kernel spectrum");
+        p->tw.alloc(twiddle_bytes(s), "twiddles");
+        p->work1.alloc((size_t)work1_elems(s) * 2 * s.elem, "work buffer 1");
+        p->work2.alloc((size_t)work2_elems(s) * 2 * s.elem, "work buffer 2");
+        if (s.elem == 4) {
+            upload_twiddles<float>(p, st);
+            build_spectrum<float>(p, st);
+        } else {
+            upload_twiddles<double>(p, st);
+            build_spectrum<double>(p, st);
+        }
+    } catch (...) {
+        delete p;
+        throw;
+    }
+    *out = p;
+}
+
+}  // namespace
+
+extern "C" {
+
+ddstress_status ddstress_plan_footprint(const ddstress_desc* desc, size_t* cached_bytes, size_t* work_bytes,
+                                        size_t* build_bytes) {
+    return guarded([&] {
+        validate(desc);
+        const Shape s = make_shape(desc);
+        if (cached_bytes) *cached_bytes = spec_bytes(s) + twiddle_bytes(s);
+        if (work_bytes)
+            *work_bytes = (size_t)(work1_elems(s) + work2_elems(s)) * 2 * s.elem + density_bytes(s);
+        if (build_bytes) *build_bytes = build_real_bytes(s) + build_cplx_bytes(s);
+    });
+}
+
+ddstress_status ddstress_plan_create(const ddstress_desc* desc, void* stream, ddstress_plan* out) {
+    return guarded([&] { create_plan(desc, static_cast<hipStream_t>(stream), out); });
+}
+
+ddstress_status ddstress_set_density(ddstress_plan plan, const void* rho, int32_t where, void* stream) {
+    return guarded([&] {
+        if (!plan) fail(DDSTRESS_E_INVALID, "plan is NULL");
+        if (!rho) fail(DDSTRESS_E_INVALID, "density pointer is NULL");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const size_t bytes = density_bytes(plan->shape);
+        if (where == DDSTRESS_DEVICE_BORROW) {
+            plan->rho = rho;
+        } else if (where == DDSTRESS_HOST || where == DDSTRESS_DEVICE_COPY) {
+            if (!plan->rho_own.p) plan->rho_own.alloc(bytes, "density buffer");
+            check_hip(hipMemcpyAsync(plan->rho_own.p, rho, bytes,
+                                     where == DDSTRESS_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st),
+                      "density copy");
+            plan->rho = plan->rho_own.p;
+        } else {
+            fail(DDSTRESS_E_INVALID, "unknown buffer location");
+        }
+        plan->have_density = true;
+    });
+}
+
+ddstress_status ddstress_stress(ddstress_plan plan, void* sigma, int32_t where, void* stream) {
+    return guarded([&] {
+        if (!plan) fail(DDSTRESS_E_INVALID, "plan is NULL");
+        if (!sigma) fail(DDSTRESS_E_INVALID, "stress pointer is NULL");
+        if (!plan->have_density) fail(DDSTRESS_E_STATE, "no density set on this plan");
+        if (where != DDSTRESS_HOST && where != DDSTRESS_DEVICE_COPY && where != DDSTRESS_DEVICE_BORROW)
+            fail(DDSTRESS_E_INVALID, "unknown buffer location");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        void* dst = sigma;
+        const size_t bytes = sigma_bytes(plan->shape);
+        if (where == DDSTRESS_HOST) {
+            if (!plan->sigma_tmp.p) plan->sigma_tmp.alloc(bytes, "stress staging buffer");
+            dst = plan->sigma_tmp.p;
+        }
+        if (plan->shape.elem == 4)
+            run_stress<float>(plan, static_cast<float*>(dst), st);
+        else
+            run_stress<double>(plan, static_cast<double*>(dst), st);
+        if (where == DDSTRESS_HOST)
+            check_hip(hipMemcpyAsync(sigma, dst, bytes, hipMemcpyDeviceToHost, st), "stress copy to host");
+    });
+}
+
+ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info) {
+    return guarded([&] {
+        if (!plan || !info) fail(DDSTRESS_E_INVALID, "NULL argument");
+        const Shape& s = plan->shape;
+        std::memset(info, 0, sizeof(*info));
+        KernelParams kp = make_kernel_params(plan->desc, 0, s.P);
+        for (int a = 0; a < 3; ++a) {
+            info->padded[a] = s.P[a];
+            info->subdiv[a] = kp.m[a];
+        }
+        info->channels = s.C;
+        info->batch = s.B;
+        info->precision = plan->desc.precision;
+        info->tile_z = s.tkz;
+        info->cached_bytes = plan->spec.bytes + plan->tw.bytes;
+        info->work_bytes = plan->work1.bytes + plan->work2.bytes + plan->rho_own.bytes + plan->sigma_tmp.bytes;
+        info->kernel_real_max = plan->re_max;
+        info->kernel_imag_max = plan->im_max;
+    });
+}
+
+ddstress_status ddstress_plan_destroy(ddstress_plan plan) {
+    return guarded([&] {
+        if (!plan) return;
+        (void)hipDeviceSynchronize();
+        delete plan;
+    });
+}
+
+ddstress_status ddstress_kernel_realspace(const ddstress_desc* desc, int32_t line, double* out, void* stream) {
+    return guarded([&] {
+        validate(desc);
+        if (line < 0 || line >= desc->n_lines) fail(DDSTRESS_E_INVALID, "line index out of range");
+        if (!out) fail(DDSTRESS_E_INVALID, "output pointer is NULL");
+        const Shape s = make_shape(desc);
+        KernelParams kp = make_kernel_params(*desc, line, s.P);
+        launch_kernel_build(kp, out, static_cast<hipStream_t>(stream));
+    });
+}
+
+const char* ddstress_last_error(void) { return g_last_error.c_str(); }
+
+const char* ddstress_version(void) { return "ddstress 0.1.0 (gfx950)"; }
+
+}  // extern "C"

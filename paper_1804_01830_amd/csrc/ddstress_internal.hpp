@@ -1,0 +1,114 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/ddstress.h"
+#include "fft_device.hpp"
+
+namespace dds {
+
+// Error plumbing: the C entry points catch these and turn them into statuses.
+struct Error {
+    ddstress_status status;
+    std::string msg;
+};
+[[noreturn]] void fail(ddstress_status s, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+inline int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// Largest supported FFT length on any axis.
+constexpr int kMaxLen = 1024;
+// Twiddle table: entry L-1+k holds exp(-2 pi i k / L) for every power of two L <= kMaxLen.
+constexpr int kTwiddleEntries = 2 * kMaxLen;
+
+template <typename T>
+void fill_twiddles(cplx<T>* host);   // kTwiddleEntries entries
+
+// Launch geometry of one pass.
+struct ColLaunch {
+    int tk;        // columns per block
+};
+struct RowLaunch {
+    int rows;      // rows per block
+};
+
+// ---- pass launchers (passes.hip) -------------------------------------------
+// Real-to-complex transform of length P = 2M along contiguous rows.
+template <typename T>
+void launch_x_r2c(int M, const T* in, cplx<T>* out, int64_t nrows, int n_in, int64_t in_stride,
+                  int64_t out_stride, const cplx<T>* tw, int rows_per_block, hipStream_t s);
+// Complex-to-real transform of length P = 2M along rows, keeping n_out reals.
+template <typename T>
+void launch_x_c2r(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
+                  int64_t out_stride, const cplx<T>* tw, int rows_per_block, hipStream_t s);
+// Complex transform of length N along a strided axis, on tiles of consecutive columns.
+struct ColGeom {
+    int ncols;             // valid columns (consecutive in memory)
+    int n_in, n_out;       // rows read (the rest are zero) and rows written
+    int64_t nouter, nplanes;
+    int64_t irs, ios, ips; // input row / outer / plane strides (elements)
+    int64_t ors, oos, ops; // output strides
+};
+template <typename T>
+void launch_col_fft(int N, bool forward, const cplx<T>* in, cplx<T>* out, const ColGeom& g,
+                    const cplx<T>* tw, int tk, hipStream_t s);
+// Fused forward z transform, contraction with the kernel spectrum and inverse z.
+struct ZGeom {
+    int ncols;             // valid kx columns
+    int ntiles;            // kx tiles (ncols rounded up to tk)
+    int nky;               // ky rows (blocks along y)
+    int nz;                // rows read and written along z
+    int C, B;              // channels and batch
+    int64_t irs, iqs, ios; // input z / plane / ky strides
+    int64_t ors, oqs, oos; // output strides (6B planes)
+};
+template <typename T>
+void launch_z_fused(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+                    const cplx<T>* tw, int tk, hipStream_t s);
+
+// Default launch geometry.
+int default_col_tk(int N, int elem_bytes);
+int default_rows(int M, int elem_bytes);
+int default_z_tk(int N, int elem_bytes);
+int col_threads(int N, int tk);
+int z_threads(int N, int tk, int elem_bytes);
+
+// ---- kernel build (kernel_build.hip) ---------------------------------------
+struct KernelParams {
+    int n[3];
+    int P[3];
+    double d[3];
+    double s[3];       // subcell edges
+    int m[3];          // subcells per axis
+    double t[3];       // unit line direction
+    double mu, nu;
+    double h_cell, h_sub;
+    double dV;
+    double near_lim;   // S * max(d)
+};
+KernelParams make_kernel_params(const ddstress_desc& desc, int line, const int P[3]);
+// 18 planes [gamma][v][Pz][Py][Px] of FP64 coefficients.
+void launch_kernel_build(const KernelParams& p, double* out, hipStream_t s);
+// Spectrum extraction: S[ky][tile][c][v][kz][tk] = Im(Khat) / P for channels 3*line..3*line+2.
+template <typename T>
+void launch_extract(const cplx<double>* kh, T* spec, int line, int C, int ncols, int64_t wx, int Py,
+                    int Pz, int tk, int ntiles, double inv_p, unsigned long long* maxbits,
+                    hipStream_t s);
+
+}  // namespace dds

@@ -1,0 +1,190 @@
+// Device-side building blocks of the power-of-two FFTs used by every pass.
+//
+// One transform of length N is done by Tc = N / E threads. Thread j owns the
+// E elements x[j + Tc*m], m = 0..E-1, in registers both before the first
+// stage and after the last one (the Stockham autosort ordering keeps that
+// distribution), so a forward transform can hand its output straight to an
+// inverse transform in registers, and the first stage loads / last stage
+// stores go to global memory with consecutive threads on consecutive rows.
+// Between stages the data goes through LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dds {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
+
+// Multiply by the twiddle w (table holds forward values exp(-2 pi i k / N));
+// the inverse transform uses its conjugate.
+template <bool FWD, typename T>
+__device__ __forceinline__ cplx<T> twmul(cplx<T> a, cplx<T> w) {
+    if (FWD) return cmul(a, w);
+    return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
+}
+
+// Multiply by -i (forward) or +i (inverse).
+template <bool FWD, typename T>
+__device__ __forceinline__ cplx<T> rot90(cplx<T> a) {
+    if (FWD) return {a.y, -a.x};
+    return {-a.y, a.x};
+}
+
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft2(cplx<T>* v) {
+    cplx<T> a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft4(cplx<T>* v) {
+    cplx<T> t0 = cadd(v[0], v[2]);
+    cplx<T> t1 = csub(v[0], v[2]);
+    cplx<T> t2 = cadd(v[1], v[3]);
+    cplx<T> t3 = rot90<FWD>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[2] = csub(t0, t2);
+    v[3] = csub(t1, t3);
+}
+
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft8(cplx<T>* v) {
+    // even/odd split: two length-4 transforms joined with the eighth roots
+    cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<FWD>(e);
+    dft4<FWD>(o);
+    const T h = T(0.70710678118654752440084436210484904);
+    // o1 * w8, o2 * w8^2 = -/+ i, o3 * w8^3, with w8 = (1 -/+ i)/sqrt 2
+    cplx<T> o1, o3;
+    if (FWD) {
+        o1 = {(o[1].x + o[1].y) * h, (o[1].y - o[1].x) * h};
+        o3 = {(o[3].y - o[3].x) * h, -(o[3].x + o[3].y) * h};
+    } else {
+        o1 = {(o[1].x - o[1].y) * h, (o[1].x + o[1].y) * h};
+        o3 = {-(o[3].x + o[3].y) * h, (o[3].x - o[3].y) * h};
+    }
+    cplx<T> o2 = rot90<FWD>(o[2]);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
+template <int R, bool FWD, typename T>
+__device__ __forceinline__ void dftR(cplx<T>* v) {
+    if constexpr (R == 2) dft2<FWD>(v);
+    else if constexpr (R == 4) dft4<FWD>(v);
+    else if constexpr (R == 8) dft8<FWD>(v);
+}
+
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// Elements per thread used for a transform of length N in the plain passes.
+constexpr int elems_for(int N) { return N <= 8 ? N : (N <= 64 ? 8 : 16); }
+// Elements per thread in the fused z kernel (six complex accumulators per
+// element must stay in registers: 8 in FP32, 4 in FP64).
+constexpr int elems_fused(int N, int elem_bytes) {
+    return elem_bytes <= 4 ? (N <= 8 ? N : 8) : (N <= 4 ? N : 4);
+}
+
+// LDS addressing of element i of transform (column / row) c.
+struct ColMajor {      // element i of column c at i*ld + c (tiles of consecutive columns)
+    int ld;
+    __device__ __forceinline__ int operator()(int i, int c) const { return i * ld + c; }
+};
+struct RowMajor {      // element i of row r at r*ld + i
+    int ld;
+    __device__ __forceinline__ int operator()(int i, int r) const { return r * ld + i; }
+};
+
+// One radix-R Stockham stage. Butterfly b = j + Tc*q (q < E/R) reads
+// x[b + r N/R], multiplies by exp(-/+ 2 pi i (b mod Ns) r / (Ns R)), applies
+// the length-R DFT and writes (b / Ns) Ns R + (b mod Ns) + r Ns.
+template <typename T, int N, int E, bool FWD, int Ns, int R, class Lay>
+__device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
+                                          const cplx<T>* __restrict__ tw) {
+    constexpr int Tc = N / E;
+    constexpr int NB = E / R;
+    constexpr bool first = (Ns == 1);
+    constexpr bool last = (Ns * R == N);
+    cplx<T> v[NB][R];
+    if constexpr (first) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = reg[q + r * NB];
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = lds[lay(j + Tc * q + r * (N / R), c)];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if constexpr (!first) {
+            const int k = (j + Tc * q) & (Ns - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[q][r] = twmul<FWD>(v[q][r], tw[k * r * (N / (Ns * R))]);
+        }
+        dftR<R, FWD>(v[q]);
+    }
+    if constexpr (last) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) reg[q + r * NB] = v[q][r];
+    } else {
+        __syncthreads();   // every thread has read its inputs (or the buffer's previous user is done)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int b = j + Tc * q;
+            const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lay(base + r * Ns, c)] = v[q][r];
+        }
+    }
+}
+
+template <typename T, int N, int E, bool FWD, int Ns, class Lay>
+__device__ __forceinline__ void fft_stages(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
+                                           const cplx<T>* __restrict__ tw) {
+    if constexpr (Ns < N) {
+        constexpr int R = cmin(cmin(8, E), N / Ns);
+        fft_stage<T, N, E, FWD, Ns, R>(reg, lds, lay, c, j, tw);
+        fft_stages<T, N, E, FWD, Ns * R>(reg, lds, lay, c, j, tw);
+    }
+}
+
+// Full transform of length N on the register distribution described above.
+// `tw` points at the table of exp(-2 pi i k / N), k < N. Every thread of the
+// block must call it (it contains barriers when N > E).
+template <typename T, int N, int E, bool FWD, class Lay>
+__device__ __forceinline__ void fft_regs(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
+                                         const cplx<T>* __restrict__ tw) {
+    static_assert(N % E == 0, "E must divide N");
+    fft_stages<T, N, E, FWD, 1>(reg, lds, lay, c, j, tw);
+}
+
+}  // namespace dds

@@ -1,0 +1,257 @@
+// Interaction coefficients on the device, in FP64 (Sec. 2.2 and 2.3).
+//
+// For one line direction t and each unit Burgers vector e_gamma,
+//   K_{v,gamma}(D) = dV / h * sigma^AB_v(p; e_gamma, t, h)
+// is the stress per unit length of a segment (Eq. 9b) times the cell volume.
+// Far cells: p = D o d (cell-centre offset) with h the cell's chord along t.
+// Near cells (|D_a| d_a <= S max d on every axis): target and source cells are
+// split into m_a subcells per axis; the coefficient is the mean over target
+// subcells of the sum over source subcells, i.e. the sum over sub-offsets
+// delta (|delta_a| < m_a) with weight prod_a (m_a - |delta_a|) / m_a^2 of the
+// subcell coefficient at p = D o d + delta o s, h the subcell chord. The
+// self-term is zero: with identical subdivision every sub-offset pair
+// +delta / -delta cancels because a centred segment's field is odd.
+//
+// The segment stress is the coordinate-free Eq. (6)-(7), evaluated at each
+// end point E with R = p - E, R_t = R + |R| t = rho + (|R| + L) t,
+// L = R.t, rho = R - L t, and |R| + L computed as |rho|^2 / (|R| - L) when
+// L < 0. Points behind the segment centre use the same segment described from
+// B to A (t -> -t, b -> -b), which keeps them off the singular ray R_t = 0.
+#include <atomic>
+#include <cmath>
+
+#include "ddstress_internal.hpp"
+
+namespace dds {
+
+namespace {
+
+// Voigt pairs (xx, yy, zz, yz, xz, xy).
+__device__ __constant__ int kVa[6] = {0, 1, 2, 1, 0, 0};
+__device__ __constant__ int kVb[6] = {0, 1, 2, 2, 2, 1};
+
+// acc[g*6+v] += coef * sigma_v at one end point for b = bsign * e_g.
+__device__ void eq6_end(const double R[3], const double t[3], double bsign, double coef,
+                        double mu, double nu, double* acc) {
+    const double Rn = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+    const double L = R[0] * t[0] + R[1] * t[1] + R[2] * t[2];
+    double rho[3] = {R[0] - L * t[0], R[1] - L * t[1], R[2] - L * t[2]};
+    const double rho2 = rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2];
+    const double rpl = (L >= 0.0) ? (Rn + L) : rho2 / (Rn - L);
+    const double Y[3] = {rho[0] + rpl * t[0], rho[1] + rpl * t[1], rho[2] + rpl * t[2]};
+    const double Y2 = Y[0] * Y[0] + Y[1] * Y[1] + Y[2] * Y[2];
+    const double inv_y2 = 1.0 / Y2;
+    const double lr = L / Rn;
+    const double pref = coef * mu / (M_PI * Y2);
+    const double k1 = 1.0 / (1.0 - nu);
+    const double k2 = 0.5 / (1.0 - nu);
+    // Y x t (its components are the triple products (e_g, Y, t))
+    const double yxt[3] = {Y[1] * t[2] - Y[2] * t[1], Y[2] * t[0] - Y[0] * t[2], Y[0] * t[1] - Y[1] * t[0]};
+    for (int g = 0; g < 3; ++g) {
+        // b = bsign e_g: b x Y and b x t
+        double bY[3], bt[3];
+        const int g1 = (g + 1) % 3, g2 = (g + 2) % 3;
+        bY[g] = 0.0;
+        bY[g1] = -bsign * Y[g2];
+        bY[g2] = bsign * Y[g1];
+        bt[g] = 0.0;
+        bt[g1] = -bsign * t[g2];
+        bt[g2] = bsign * t[g1];
+        const double trip = bsign * yxt[g];
+        for (int v = 0; v < 6; ++v) {
+            const int a = kVa[v], c = kVb[v];
+            const double phi = 2.0 * inv_y2 * (rho[a] * Y[c] + Y[a] * rho[c] + lr * Y[a] * Y[c]);
+            const double s1 = 0.5 * (bY[a] * t[c] + bY[c] * t[a]);
+            const double s2 = 0.5 * (bt[a] * Y[c] + bt[c] * Y[a]);
+            const double dl = (a == c) ? 1.0 : 0.0;
+            acc[g * 6 + v] += pref * (s1 - k1 * s2 - k2 * trip * (dl + t[a] * t[c] + phi));
+        }
+    }
+}
+
+// acc += coef * sigma^AB(p) of the segment of length h along t centred at 0.
+__device__ void segment(const double p[3], double h, const double t[3], double coef, double mu,
+                        double nu, double* acc) {
+    const double hh = 0.5 * h;
+    const double pt = p[0] * t[0] + p[1] * t[1] + p[2] * t[2];
+    const double RB[3] = {p[0] - hh * t[0], p[1] - hh * t[1], p[2] - hh * t[2]};
+    const double RA[3] = {p[0] + hh * t[0], p[1] + hh * t[1], p[2] + hh * t[2]};
+    if (pt >= 0.0) {
+        eq6_end(RB, t, 1.0, coef, mu, nu, acc);
+        eq6_end(RA, t, 1.0, -coef, mu, nu, acc);
+    } else {
+        const double tr[3] = {-t[0], -t[1], -t[2]};
+        eq6_end(RA, tr, -1.0, coef, mu, nu, acc);
+        eq6_end(RB, tr, -1.0, -coef, mu, nu, acc);
+    }
+}
+
+__device__ __forceinline__ bool wrap_offset(int i, int n, int P, int& off) {
+    if (i < n) { off = i; return true; }
+    if (i > P - n) { off = i - P; return true; }
+    return false;
+}
+
+__global__ void __launch_bounds__(256) k_kernel_build(double* __restrict__ out, KernelParams kp,
+                                                      int64_t plane) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= plane) return;
+    const int ix = (int)(idx % kp.P[0]);
+    const int iy = (int)((idx / kp.P[0]) % kp.P[1]);
+    const int iz = (int)(idx / ((int64_t)kp.P[0] * kp.P[1]));
+    double acc[18];
+    for (int q = 0; q < 18; ++q) acc[q] = 0.0;
+    int D[3];
+    const bool inside = wrap_offset(ix, kp.n[0], kp.P[0], D[0]) && wrap_offset(iy, kp.n[1], kp.P[1], D[1]) &&
+                        wrap_offset(iz, kp.n[2], kp.P[2], D[2]);
+    if (inside && (D[0] != 0 || D[1] != 0 || D[2] != 0)) {
+        bool near = true;
+        for (int a = 0; a < 3; ++a) near = near && (fabs((double)D[a]) * kp.d[a] <= kp.near_lim);
+        if (!near) {
+            const double p[3] = {D[0] * kp.d[0], D[1] * kp.d[1], D[2] * kp.d[2]};
+            segment(p, kp.h_cell, kp.t, kp.dV / kp.h_cell, kp.mu, kp.nu, acc);
+        } else {
+            for (int dz = -(kp.m[2] - 1); dz < kp.m[2]; ++dz)
+                for (int dy = -(kp.m[1] - 1); dy < kp.m[1]; ++dy)
+                    for (int dx = -(kp.m[0] - 1); dx < kp.m[0]; ++dx) {
+                        const double wx = (double)(kp.m[0] - abs(dx)) / (double)(kp.m[0] * kp.m[0]);
+                        const double wy = (double)(kp.m[1] - abs(dy)) / (double)(kp.m[1] * kp.m[1]);
+                        const double wz = (double)(kp.m[2] - abs(dz)) / (double)(kp.m[2] * kp.m[2]);
+                        const double w = wx * wy * wz;
+                        const double p[3] = {D[0] * kp.d[0] + dx * kp.s[0], D[1] * kp.d[1] + dy * kp.s[1],
+                                             D[2] * kp.d[2] + dz * kp.s[2]};
+                        segment(p, kp.h_sub, kp.t, w * kp.dV / kp.h_sub, kp.mu, kp.nu, acc);
+                    }
+        }
+    }
+    for (int q = 0; q < 18; ++q) out[q * plane + idx] = acc[q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_extract(const cplx<double>* __restrict__ kh, T* __restrict__ spec,
+                                                 int line, int C, int ncols, int64_t wx, int Py, int Pz,
+                                                 int tk, int ntiles, double inv_p,
+                                                 unsigned long long* __restrict__ maxbits) {
+    // one thread per (gamma, v, kz, ky, column of the tiled kx range)
+    const int64_t kxr = (int64_t)ntiles * tk;
+    const int64_t total = 18LL * Pz * Py * kxr;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double re = 0.0, im = 0.0;
+    if (idx < total) {
+        const int64_t kx = idx % kxr;
+        int64_t r = idx / kxr;
+        const int ky = (int)(r % Py);
+        r /= Py;
+        const int kz = (int)(r % Pz);
+        const int gv = (int)(r / Pz);          // gamma * 6 + v
+        const int g = gv / 6, v = gv % 6;
+        if (kx < ncols) {
+            const cplx<double> val = kh[(((int64_t)gv * Pz + kz) * Py + ky) * wx + kx];
+            re = fabs(val.x);
+            im = fabs(val.y);
+            const int tile = (int)(kx / tk), col = (int)(kx % tk);
+            const int ch = 3 * line + g;
+            const int64_t o = (((((int64_t)ky * ntiles + tile) * C + ch) * 6 + v) * Pz + kz) * tk + col;
+            spec[o] = (T)(val.y * inv_p);
+        } else {
+            const int tile = (int)(kx / tk), col = (int)(kx % tk);
+            const int ch = 3 * line + g;
+            const int64_t o = (((((int64_t)ky * ntiles + tile) * C + ch) * 6 + v) * Pz + kz) * tk + col;
+            spec[o] = T(0);
+        }
+    }
+    // block maxima of |Re| and |Im| (non-negative doubles order like their bit patterns)
+    __shared__ double sre[256], sim[256];
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sre[threadIdx.x] = fmax(sre[threadIdx.x], sre[threadIdx.x + w]);
+            sim[threadIdx.x] = fmax(sim[threadIdx.x], sim[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&maxbits[0], (unsigned long long)__double_as_longlong(sre[0]));
+        atomicMax(&maxbits[1], (unsigned long long)__double_as_longlong(sim[0]));
+    }
+}
+
+double chord(const double box[3], const double t[3]) {
+    double best = INFINITY;
+    for (int a = 0; a < 3; ++a)
+        if (t[a] != 0.0) best = std::fmin(best, box[a] / std::fabs(t[a]));
+    return best;
+}
+
+}  // namespace
+
+KernelParams make_kernel_params(const ddstress_desc& desc, int line, const int P[3]) {
+    KernelParams kp{};
+    double dmin = desc.d[0], dmax = desc.d[0];
+    for (int a = 0; a < 3; ++a) {
+        kp.n[a] = desc.n[a];
+        kp.P[a] = P[a];
+        kp.d[a] = desc.d[a];
+        dmin = std::fmin(dmin, desc.d[a]);
+        dmax = std::fmax(dmax, desc.d[a]);
+    }
+    for (int a = 0; a < 3; ++a) {
+        kp.m[a] = std::max(1, (int)std::floor(desc.d[a] / dmin + 0.5));
+        kp.s[a] = desc.d[a] / kp.m[a];
+    }
+    const double* tl = desc.t[line];
+    const double tn = std::sqrt(tl[0] * tl[0] + tl[1] * tl[1] + tl[2] * tl[2]);
+    for (int a = 0; a < 3; ++a) kp.t[a] = tl[a] / tn;
+    kp.mu = desc.mu;
+    kp.nu = desc.nu;
+    kp.h_cell = chord(kp.d, kp.t);
+    kp.h_sub = chord(kp.s, kp.t);
+    kp.dV = desc.d[0] * desc.d[1] * desc.d[2];
+    const int S = desc.near_shells == 0 ? 2 : desc.near_shells;
+    kp.near_lim = S * dmax;
+    return kp;
+}
+
+void launch_kernel_build(const KernelParams& kp, double* out, hipStream_t s) {
+    const int64_t plane = (int64_t)kp.P[0] * kp.P[1] * kp.P[2];
+    const int64_t blocks = (plane + 255) / 256;
+    hipLaunchKernelGGL(k_kernel_build, dim3((unsigned)blocks), dim3(256), 0, s, out, kp, plane);
+    check_hip(hipGetLastError(), "kernel build launch");
+}
+
+template <typename T>
+void launch_extract(const cplx<double>* kh, T* spec, int line, int C, int ncols, int64_t wx, int Py,
+                    int Pz, int tk, int ntiles, double inv_p, unsigned long long* maxbits,
+                    hipStream_t s) {
+    const int64_t total = 18LL * Pz * Py * (int64_t)ntiles * tk;
+    const int64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL((k_extract<T>), dim3((unsigned)blocks), dim3(256), 0, s, kh, spec, line, C, ncols,
+                       wx, Py, Pz, tk, ntiles, inv_p, maxbits);
+    check_hip(hipGetLastError(), "spectrum extraction launch");
+}
+
+template void launch_extract<float>(const cplx<double>*, float*, int, int, int, int64_t, int, int, int,
+                                    int, double, unsigned long long*, hipStream_t);
+template void launch_extract<double>(const cplx<double>*, double*, int, int, int, int64_t, int, int, int,
+                                     int, double, unsigned long long*, hipStream_t);
+
+template <typename T>
+void fill_twiddles(cplx<T>* host) {
+    // entry L-1+k = exp(-2 pi i k / L), evaluated in long double and rounded once
+    host[0] = {T(1), T(0)};
+    for (int L = 2; L <= kMaxLen; L <<= 1) {
+        for (int k = 0; k < L; ++k) {
+            const long double pi = 3.141592653589793238462643383279502884L;
+            const long double a = 2.0L * pi * (long double)k / (long double)L;
+            const long double c = cosl(a), sn = sinl(a);
+            host[L - 1 + k] = {(T)c, (T)(-sn)};
+        }
+    }
+    host[kTwiddleEntries - 1] = {T(1), T(0)};
+}
+template void fill_twiddles<float>(cplx<float>*);
+template void fill_twiddles<double>(cplx<double>*);
+
+}  // namespace dds

@@ -1,0 +1,364 @@
+// The five passes of one stress evaluation (zero-padded convolution of
+// Eq. (10) by the convolution theorem, Sec. 2.3):
+//   x: real-to-complex along x      (rows contiguous)
+//   y: complex along y              (strided, tiles of consecutive kx)
+//   z: forward z, per-wavevector contraction with the kernel spectrum,
+//      inverse z                    (strided, fused, accumulators in registers)
+//   y: inverse, cropped to Ny
+//   x: complex-to-real, cropped to Nx
+// The same x and strided kernels, instantiated in FP64, transform the
+// interaction coefficients when a plan is built.
+#include "ddstress_internal.hpp"
+
+namespace dds {
+
+// ----------------------------------------------------------------------------
+// x: real-to-complex of length P = 2M. Row r has n_in reals (the rest of the P
+// inputs are zero). The reals are packed in pairs, z[m] = x[2m] + i x[2m+1],
+// transformed with length M and split into the M+1 non-redundant outputs
+//   X[k] = (Z[k] + conj Z[M-k]) / 2 - (i/2) exp(-2 pi i k / P) (Z[k] - conj Z[M-k]).
+// ----------------------------------------------------------------------------
+template <typename T, int M, int E>
+__global__ void __launch_bounds__(512) k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
+                                               int64_t nrows, int n_in, int64_t in_stride,
+                                               int64_t out_stride, const cplx<T>* __restrict__ tw,
+                                               int rows_per_block) {
+    constexpr int Tc = M / E;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int j = threadIdx.x % Tc;
+    const int rl = threadIdx.x / Tc;
+    const int64_t row = (int64_t)blockIdx.x * rows_per_block + rl;
+    const bool valid = row < nrows;
+    const RowMajor lay{M + 1};
+    const T* src = in + (valid ? row : 0) * in_stride;
+    cplx<T> reg[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i0 = 2 * (j + Tc * m);
+        T a = T(0), b = T(0);
+        if (valid && i0 < n_in) a = src[i0];
+        if (valid && i0 + 1 < n_in) b = src[i0 + 1];
+        reg[m] = {a, b};
+    }
+    fft_regs<T, M, E, true>(reg, lds, lay, rl, j, tw + (M - 1));
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) lds[lay(j + Tc * m, rl)] = reg[m];
+    __syncthreads();
+    if (!valid) return;
+    cplx<T>* dst = out + row * out_stride;
+    const cplx<T>* tw2 = tw + (2 * M - 1);
+    const T half = T(0.5);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = j + Tc * m;
+        const cplx<T> zk = lds[lay(k, rl)];
+        const cplx<T> zm = cconj(lds[lay((M - k) & (M - 1), rl)]);
+        const cplx<T> e = cadd(zk, zm);
+        const cplx<T> wd = cmul(tw2[k], csub(zk, zm));          // W_P^k (Z[k] - conj Z[M-k])
+        dst[k] = {half * (e.x + wd.y), half * (e.y - wd.x)};   // e/2 - (i/2) wd
+    }
+    if (j == 0) {
+        const cplx<T> z0 = lds[lay(0, rl)];
+        dst[M] = {z0.x - z0.y, T(0)};
+    }
+}
+
+// ----------------------------------------------------------------------------
+// x: complex-to-real of length P = 2M (unnormalised inverse), from the M+1
+// non-redundant inputs of each row, keeping the first n_out reals:
+//   Z'[k] = (X[k] + conj X[M-k]) + i exp(+2 pi i k / P) (X[k] - conj X[M-k]),
+//   z = inverse length-M transform of Z',  x[2m] = Re z[m], x[2m+1] = Im z[m].
+// ----------------------------------------------------------------------------
+template <typename T, int M, int E>
+__global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
+                                               int64_t nrows, int n_out, int64_t in_stride,
+                                               int64_t out_stride, const cplx<T>* __restrict__ tw,
+                                               int rows_per_block) {
+    constexpr int Tc = M / E;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int j = threadIdx.x % Tc;
+    const int rl = threadIdx.x / Tc;
+    const int64_t row = (int64_t)blockIdx.x * rows_per_block + rl;
+    const bool valid = row < nrows;
+    const RowMajor lay{M + 1};
+    const cplx<T>* src = in + (valid ? row : 0) * in_stride;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = j + Tc * m;
+        lds[lay(k, rl)] = valid ? src[k] : cplx<T>{T(0), T(0)};
+    }
+    if (j == 0) lds[lay(M, rl)] = valid ? src[M] : cplx<T>{T(0), T(0)};
+    __syncthreads();
+    const cplx<T>* tw2 = tw + (2 * M - 1);
+    cplx<T> reg[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int k = j + Tc * m;
+        const cplx<T> xk = lds[lay(k, rl)];
+        const cplx<T> xm = cconj(lds[lay(M - k, rl)]);
+        const cplx<T> e = cadd(xk, xm);
+        const cplx<T> wd = twmul<false>(csub(xk, xm), tw2[k]);   // exp(+2 pi i k/P) (X[k] - conj X[M-k])
+        reg[m] = {e.x - wd.y, e.y + wd.x};                       // e + i wd
+    }
+    fft_regs<T, M, E, false>(reg, lds, lay, rl, j, tw + (M - 1));
+    if (!valid) return;
+    T* dst = out + row * out_stride;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i0 = 2 * (j + Tc * m);
+        if (i0 < n_out) dst[i0] = reg[m].x;
+        if (i0 + 1 < n_out) dst[i0 + 1] = reg[m].y;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Complex transform of length N along a strided axis. A block owns `tk`
+// consecutive columns (contiguous in memory) of one (outer, plane) pair and
+// all N rows of them; rows >= n_in are zero, rows >= n_out are not written.
+// Every global load of a block precedes its first store, so in == out works.
+// ----------------------------------------------------------------------------
+template <typename T, int N, int E, bool FWD>
+__global__ void __launch_bounds__(512) k_col_fft(const cplx<T>* in, cplx<T>* out, ColGeom g,
+                                                 const cplx<T>* __restrict__ tw, int tk,
+                                                 int64_t ntiles) {
+    constexpr int Tc = N / E;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int c = threadIdx.x % tk;
+    const int j = threadIdx.x / tk;
+    int64_t bid = blockIdx.x;
+    const int64_t tile = bid % ntiles;
+    bid /= ntiles;
+    const int64_t outer = bid % g.nouter;
+    const int64_t plane = bid / g.nouter;
+    const int64_t col = tile * tk + c;
+    const bool valid = col < g.ncols;
+    const cplx<T>* src = in + plane * g.ips + outer * g.ios + (valid ? col : 0);
+    const int irs = (int)g.irs, ors = (int)g.ors;   // in-block offsets fit in 32 bits (N * stride < 2^31)
+    cplx<T> reg[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = j + Tc * m;
+        reg[m] = (valid && i < g.n_in) ? src[i * irs] : cplx<T>{T(0), T(0)};
+    }
+    fft_regs<T, N, E, FWD>(reg, lds, ColMajor{tk}, c, j, tw + (N - 1));
+    if (!valid) return;
+    cplx<T>* dst = out + plane * g.ops + outer * g.oos + col;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i = j + Tc * m;
+        if (i < g.n_out) dst[i * ors] = reg[m];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Fused z pass. A block owns `tk` consecutive kx columns at one ky. For every
+// realisation b it transforms the C density columns along z (length N, nz
+// inputs), accumulates the six stress spectra
+//     sigma^_v(k) = sum_c i S_{v,c}(k) rho^_c(k)        (K^ = i S, K odd)
+// in registers with a fixed channel order, and transforms each back along z,
+// writing the first nz rows. The spectrum tile of the block is stored
+// contiguously as [c][v][kz][tk].
+// ----------------------------------------------------------------------------
+template <typename T, int N, int E>
+__global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                 const T* __restrict__ spec, ZGeom g,
+                                                 const cplx<T>* __restrict__ tw, int tk) {
+    constexpr int Tc = N / E;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int c = threadIdx.x % tk;
+    const int j = threadIdx.x / tk;
+    const int tile = blockIdx.x % g.ntiles;
+    const int ky = blockIdx.x / g.ntiles;
+    const int col = tile * tk + c;
+    const bool valid = col < g.ncols;
+    const int colc = valid ? col : 0;
+    const ColMajor lay{tk};
+    const cplx<T>* twN = tw + (N - 1);
+    const int irs = (int)g.irs, ors = (int)g.ors;    // in-block offsets fit in 32 bits
+    const T* sp = spec + ((int64_t)ky * g.ntiles + tile) * (int64_t)g.C * 6 * N * tk + c;
+    const cplx<T>* in_b = in + (int64_t)ky * g.ios + colc;
+    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
+    for (int b = 0; b < g.B; ++b) {
+        cplx<T> acc[6][E];
+#pragma unroll
+        for (int v = 0; v < 6; ++v)
+#pragma unroll
+            for (int m = 0; m < E; ++m) acc[v][m] = {T(0), T(0)};
+        for (int ch = 0; ch < g.C; ++ch) {
+            const cplx<T>* src = in_b + (int64_t)(b * g.C + ch) * g.iqs;
+            cplx<T> reg[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const int z = j + Tc * m;
+                reg[m] = (valid && z < g.nz) ? src[z * irs] : cplx<T>{T(0), T(0)};
+            }
+            fft_regs<T, N, E, true>(reg, lds, lay, c, j, twN);
+            const T* spc = sp + (int64_t)ch * 6 * N * tk + j * tk;
+#pragma unroll
+            for (int v = 0; v < 6; ++v)
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const T s = spc[(v * N + Tc * m) * tk];
+                    acc[v][m].x -= s * reg[m].y;
+                    acc[v][m].y += s * reg[m].x;
+                }
+        }
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            fft_regs<T, N, E, false>(acc[v], lds, lay, c, j, twN);
+            if (valid) {
+                cplx<T>* dst = out_b + (int64_t)(b * 6 + v) * g.oqs;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int z = j + Tc * m;
+                    if (z < g.nz) dst[z * ors] = acc[v][m];
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Launch geometry and dispatch over the power-of-two lengths.
+// ----------------------------------------------------------------------------
+int col_threads(int N, int tk) { return tk * (N / elems_for(N)); }
+int z_threads(int N, int tk, int elem_bytes) { return tk * (N / elems_fused(N, elem_bytes)); }
+
+int default_col_tk(int N, int elem_bytes) {
+    const int tc = N / elems_for(N);
+    const int tk_min = elem_bytes <= 4 ? 16 : 8;
+    int tk = 256 / tc;
+    if (tk < tk_min) tk = tk_min;
+    while (tk > 1 && tk * tc > 512) tk /= 2;
+    while (tk > 1 && (int64_t)N * tk * 2 * elem_bytes > 64 * 1024) tk /= 2;
+    return tk;
+}
+
+int default_rows(int M, int elem_bytes) {
+    const int tc = M / elems_for(M);
+    int rows = 256 / tc;
+    if (rows < 1) rows = 1;
+    while (rows > 1 && (int64_t)rows * (M + 1) * 2 * elem_bytes > 64 * 1024) rows /= 2;
+    return rows;
+}
+
+int default_z_tk(int N, int elem_bytes) {
+    const int tc = N / elems_fused(N, elem_bytes);
+    const int tk_min = elem_bytes <= 4 ? 16 : 8;
+    int tk = 256 / tc;
+    if (tk < tk_min) tk = tk_min;
+    while (tk > 1 && tk * tc > 512) tk /= 2;
+    return tk;
+}
+
+#define DDS_FOR_LENGTHS(X) X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+
+template <typename T>
+void launch_x_r2c(int M, const T* in, cplx<T>* out, int64_t nrows, int n_in, int64_t in_stride,
+                  int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
+    if (nrows <= 0) return;
+    const int64_t blocks = (nrows + rows - 1) / rows;
+    const size_t lds = (size_t)rows * (M + 1) * sizeof(cplx<T>);
+    switch (M) {
+#define X_CASE(L)                                                                              \
+    case L: {                                                                                  \
+        constexpr int E = elems_for(L);                                                        \
+        hipLaunchKernelGGL((k_x_r2c<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, \
+                           in, out, nrows, n_in, in_stride, out_stride, tw, rows);             \
+        break;                                                                                 \
+    }
+        DDS_FOR_LENGTHS(X_CASE)
+#undef X_CASE
+        default: fail(DDSTRESS_E_UNSUPPORTED, "x transform length not supported");
+    }
+    check_hip(hipGetLastError(), "x r2c launch");
+}
+
+template <typename T>
+void launch_x_c2r(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
+                  int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
+    if (nrows <= 0) return;
+    const int64_t blocks = (nrows + rows - 1) / rows;
+    const size_t lds = (size_t)rows * (M + 1) * sizeof(cplx<T>);
+    switch (M) {
+#define X_CASE(L)                                                                              \
+    case L: {                                                                                  \
+        constexpr int E = elems_for(L);                                                        \
+        hipLaunchKernelGGL((k_x_c2r<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, \
+                           in, out, nrows, n_out, in_stride, out_stride, tw, rows);            \
+        break;                                                                                 \
+    }
+        DDS_FOR_LENGTHS(X_CASE)
+#undef X_CASE
+        default: fail(DDSTRESS_E_UNSUPPORTED, "x transform length not supported");
+    }
+    check_hip(hipGetLastError(), "x c2r launch");
+}
+
+template <typename T>
+void launch_col_fft(int N, bool forward, const cplx<T>* in, cplx<T>* out, const ColGeom& g,
+                    const cplx<T>* tw, int tk, hipStream_t s) {
+    const int64_t ntiles = (g.ncols + tk - 1) / tk;
+    const int64_t blocks = ntiles * g.nouter * g.nplanes;
+    if (blocks <= 0) return;
+    if (blocks > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
+    const size_t lds = (size_t)N * tk * sizeof(cplx<T>);
+    switch (N) {
+#define C_CASE(L)                                                                              \
+    case L: {                                                                                  \
+        constexpr int E = elems_for(L);                                                        \
+        if (forward)                                                                           \
+            hipLaunchKernelGGL((k_col_fft<T, L, E, true>), dim3((unsigned)blocks), dim3(tk * (L / E)), \
+                               lds, s, in, out, g, tw, tk, ntiles);                            \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_col_fft<T, L, E, false>), dim3((unsigned)blocks), dim3(tk * (L / E)), \
+                               lds, s, in, out, g, tw, tk, ntiles);                            \
+        break;                                                                                 \
+    }
+        DDS_FOR_LENGTHS(C_CASE)
+#undef C_CASE
+        default: fail(DDSTRESS_E_UNSUPPORTED, "column transform length not supported");
+    }
+    check_hip(hipGetLastError(), "column fft launch");
+}
+
+template <typename T>
+void launch_z_fused(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+                    const cplx<T>* tw, int tk, hipStream_t s) {
+    const int64_t blocks = (int64_t)g.ntiles * g.nky;
+    if (blocks <= 0) return;
+    const size_t lds = (size_t)N * tk * sizeof(cplx<T>);
+    switch (N) {
+#define Z_CASE(L)                                                                              \
+    case L: {                                                                                  \
+        constexpr int E = elems_fused(L, (int)sizeof(T));                                      \
+        hipLaunchKernelGGL((k_z_fused<T, L, E>), dim3((unsigned)blocks), dim3(tk * (L / E)), lds, s, \
+                           in, out, spec, g, tw, tk);                                          \
+        break;                                                                                 \
+    }
+        DDS_FOR_LENGTHS(Z_CASE)
+#undef Z_CASE
+        default: fail(DDSTRESS_E_UNSUPPORTED, "z transform length not supported");
+    }
+    check_hip(hipGetLastError(), "fused z launch");
+}
+
+#define INSTANTIATE(T)                                                                         \
+    template void launch_x_r2c<T>(int, const T*, cplx<T>*, int64_t, int, int64_t, int64_t,       \
+                                  const cplx<T>*, int, hipStream_t);                           \
+    template void launch_x_c2r<T>(int, const cplx<T>*, T*, int64_t, int, int64_t, int64_t,       \
+                                  const cplx<T>*, int, hipStream_t);                           \
+    template void launch_col_fft<T>(int, bool, const cplx<T>*, cplx<T>*, const ColGeom&,         \
+                                    const cplx<T>*, int, hipStream_t);                         \
+    template void launch_z_fused<T>(int, const cplx<T>*, cplx<T>*, const T*, const ZGeom&,       \
+                                    const cplx<T>*, int, hipStream_t);
+INSTANTIATE(float)
+INSTANTIATE(double)
+#undef INSTANTIATE
+
+}  // namespace dds

@@ -1,0 +1,37 @@
+"""Helpers shared by the GPU tests: run the HIP path through the C ABI on a
+workload dict and compare with oracle results."""
+import numpy as np
+
+
+def gpu_stress(w, precision=64, near_shells=0, where_rho=None):
+    """sigma (B, 6, Nz, Ny, Nx) as float64 numpy, computed by the HIP library."""
+    import torch
+    from paper_1804_01830_amd import binding as B
+    rho = np.asarray(w["rho"])
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision,
+                       batch=rho.shape[0], near_shells=near_shells)
+    plan = B.Plan(desc)
+    dt = torch.float32 if precision == 32 else torch.float64
+    r = torch.from_numpy(rho).to(device="cuda", dtype=dt).contiguous()
+    plan.set_density(r, where=B.DEVICE_BORROW if where_rho is None else where_rho)
+    out = plan.new_output()
+    plan.stress(out)
+    torch.cuda.synchronize()
+    res = out.double().cpu().numpy()
+    plan.close()
+    return res
+
+
+def rel_l2(got, ref):
+    """Relative L2 error per Voigt component (axis -4 of (..., 6, Nz, Ny, Nx)
+    or axis 0 of (6, T)) and over the whole tensor. A component whose reference
+    norm is below 1e-3 of the whole norm is measured against the whole norm."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    whole = np.linalg.norm(ref)
+    comp = []
+    for v in range(6):
+        g = np.take(got, v, axis=-4 if got.ndim >= 4 else 0)
+        r = np.take(ref, v, axis=-4 if ref.ndim >= 4 else 0)
+        comp.append(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-3 * whole))
+    return np.array(comp), np.linalg.norm(got - ref) / whole

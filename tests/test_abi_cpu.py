@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function ``include/ddstress.h`` declares, and validates descriptors
+(ddstress_plan_footprint does no device work)."""
+import os
+import re
+
+import pytest
+
+from paper_1804_01830_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "ddstress.h")).read()
+    return sorted(set(re.findall(r"\b(ddstress_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_exports():
+    assert sorted(B.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.ddstress_version().decode().startswith("ddstress")
+
+
+def _desc(**kw):
+    base = dict(n=(8, 8, 4), d=(1, 1, 2), mu=1.0, nu=0.3, lines=[(0, 0, 1)], precision=32, batch=1)
+    base.update(kw)
+    return B.make_desc(**base)
+
+
+def test_footprint_of_a_valid_descriptor():
+    cached, work, build = B.footprint(_desc())
+    # kernel spectrum: 6 C (Wx tiles) Py Pz floats, at least 6*3*9*16*8 values
+    assert cached >= 6 * 3 * 9 * 16 * 8 * 4 and work > 0 and build > 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=(0, 8, 4)), dict(d=(1, -1, 2)), dict(d=(1, float("nan"), 2)), dict(mu=0.0), dict(nu=0.5),
+    dict(nu=-1.0), dict(lines=[]), dict(lines=[(0, 0, 0)]), dict(lines=[(0, 0, 1)] * 4), dict(precision=16),
+    dict(batch=0), dict(near_shells=-1),
+])
+def test_invalid_descriptors_are_rejected(kw):
+    with pytest.raises(B.DDStressError) as e:
+        B.footprint(_desc(**kw))
+    assert e.value.status == B.E_INVALID
+    assert B.load().ddstress_last_error().decode()
+
+
+def test_unsupported_sizes_and_flags():
+    for kw in (dict(n=(513, 8, 8)), dict(flags=1)):
+        with pytest.raises(B.DDStressError) as e:
+            B.footprint(_desc(**kw))
+        assert e.value.status == B.E_UNSUPPORTED
+
+
+def test_padded_lengths():
+    assert B.padded_lengths((32, 128, 1)) == (64, 256, 2)
+    assert B.padded_lengths((5, 3, 7)) == (16, 8, 16)

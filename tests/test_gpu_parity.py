@@ -1,0 +1,134 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances: relative L2 error per stress component and over the whole tensor
+<= 1e-12 for the FP64 path and <= 1e-5 for the FP32 path (FP32 transforms and
+contraction, FP64 interaction coefficients and their transform).
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import gpu_stress, rel_l2
+from oracle import stress_direct, interaction_kernel, KernelGeometry
+from paper_1804_01830_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {64: 1e-12, 32: 1e-5}
+TILT = W.mixed_line()
+DIAG = (0.0, 1.0 / np.sqrt(2.0), 1.0 / np.sqrt(2.0))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# Full-field cases: ragged sizes, several kx tiles, batches, one to three line
+# directions, anisotropic cells (subdivision along one or two axes).
+CASES = {
+    "disk-edge-32x32x4": lambda: W.disk_edge(),
+    "rand-5x3x7-L3": lambda: W.random_field((5, 3, 7), n_lines=3, seed=1, d=(1.0, 1.5, 2.0)),
+    "rand-17x9x3-L2-B2": lambda: W.random_field((17, 9, 3), n_lines=2, batch=2, seed=2, d=(1.0, 1.0, 3.0)),
+    "rand-33x20x9-L2": lambda: W.random_field((33, 20, 9), n_lines=2, seed=3, d=(2.0, 1.0, 1.0)),
+    "rand-1x1x1": lambda: W.random_field((1, 1, 1), n_lines=1, seed=4),
+    "rand-1x6x2": lambda: W.random_field((1, 6, 2), n_lines=1, seed=5, d=(1.0, 1.0, 2.0)),
+    "rand-40x1x12-diag": lambda: W.random_field((40, 1, 12), seed=6, d=(1.0, 1.0, 1.0), lines=[DIAG]),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _case(name):
+    w = CASES[name]()
+    ref = np.stack([stress_direct(w["rho"][b], w["d"], w["lines"], w["mu"], w["nu"])
+                    for b in range(w["rho"].shape[0])])
+    return w, ref
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_field_parity(name, precision):
+    w, ref = _case(name)
+    _say(f"[parity] {name} precision={precision} n={w['n']} B={w['rho'].shape[0]}")
+    got = gpu_stress(w, precision)
+    comp, whole = rel_l2(got, ref)
+    _say(f"  rel L2 per component {np.array2string(comp, precision=2)} whole {whole:.2e}")
+    assert np.all(comp <= TOL[precision]) and whole <= TOL[precision]
+
+
+def test_zero_density_gives_exact_zero():
+    w = W.random_field((9, 7, 5), n_lines=2, seed=7)
+    w["rho"][:] = 0.0
+    for prec in (32, 64):
+        assert np.all(gpu_stress(w, prec) == 0.0)
+
+
+def test_kernel_realspace_matches_oracle_entrywise():
+    import torch
+    from paper_1804_01830_amd import binding as B
+    n, d = (6, 5, 4), (1.0, 1.5, 2.0)
+    lines = [(0.0, 0.0, 1.0), TILT, DIAG]
+    desc = B.make_desc(n, d, 1.3, 0.27, lines, precision=64)
+    P = B.padded_lengths(n)
+    ax = [np.where(np.arange(P[a]) < n[a], np.arange(P[a]), np.arange(P[a]) - P[a]) for a in range(3)]
+    valid = [(np.arange(P[a]) < n[a]) | (np.arange(P[a]) > P[a] - n[a]) for a in range(3)]
+    gz, gy, gx = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    vz, vy, vx = np.meshgrid(valid[2], valid[1], valid[0], indexing="ij")
+    mask = vz & vy & vx
+    offs = np.stack([gx[mask], gy[mask], gz[mask]], axis=-1)
+    for l, t in enumerate(lines):
+        out = torch.empty((3, 6, P[2], P[1], P[0]), dtype=torch.float64, device="cuda")
+        B.kernel_realspace(desc, l, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ref = interaction_kernel(KernelGeometry(d=d, t=t, mu=1.3, nu=0.27), offs)      # (M, 6, 3)
+        g = np.transpose(got, (2, 3, 4, 1, 0))[mask]                                  # (M, 6, 3)
+        assert np.all(got[:, :, ~mask] == 0.0)
+        err = np.abs(g - ref).max() / np.abs(ref).max()
+        _say(f"[kernel] line {l}: max abs err / max = {err:.2e}")
+        assert err < 1e-13
+
+
+def test_impulse_response_is_the_kernel_slice():
+    n = (12, 10, 6)
+    d = (1.0, 1.0, 2.0)
+    w = W.random_field(n, n_lines=2, seed=0, d=d)
+    w["rho"][:] = 0.0
+    src = (4, 7, 2)
+    w["rho"][0, 4, src[2], src[1], src[0]] = 1.0          # line 1 (tilted), gamma = y
+    got = gpu_stress(w, 64)[0]
+    gz, gy, gx = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    offs = np.stack([gx.ravel() - src[0], gy.ravel() - src[1], gz.ravel() - src[2]], axis=-1)
+    K = interaction_kernel(KernelGeometry(d=d, t=tuple(w["lines"][1]), mu=w["mu"], nu=w["nu"]), offs)
+    ref = K[:, :, 1].T.reshape(6, *got.shape[1:])
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_disk_mixed_128_sampled_targets(precision):
+    """Full-size disk with mixed Burgers vectors (128 x 128 x 32, dz = 2 dx)
+    in the launch configuration the benchmark times, checked on sampled cells
+    (corners, faces, disk centre and random cells) against the direct sum."""
+    w = W.disk_mixed()
+    rng = np.random.default_rng(21)
+    tg = np.array([[0, 0, 0], [127, 127, 31], [64, 63, 16], [127, 0, 15], [60, 70, 0], [3, 90, 31]]
+                  + [[rng.integers(128), rng.integers(128), rng.integers(32)] for _ in range(6)])
+    ref = stress_direct(w["rho"][0], w["d"], w["lines"], w["mu"], w["nu"], targets=tg)
+    got = gpu_stress(w, precision)[0][:, tg[:, 2], tg[:, 1], tg[:, 0]]
+    comp, whole = rel_l2(got, ref)
+    _say(f"[disk-mixed-128] precision={precision} per component {np.array2string(comp, precision=2)} "
+         f"whole {whole:.2e}")
+    assert np.all(comp <= TOL[precision]) and whole <= TOL[precision]
+
+
+def test_stress_before_density_is_a_state_error():
+    from paper_1804_01830_amd import binding as B
+    desc = B.make_desc((4, 4, 4), (1, 1, 1), 1.0, 0.3, [(0, 0, 1)], precision=32)
+    plan = B.Plan(desc)
+    out = plan.new_output()
+    with pytest.raises(B.DDStressError) as e:
+        plan.stress(out)
+    assert e.value.status == B.E_STATE
+    plan.close()
