@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of the stress evaluation (one GPU).
+
+A step is one full evaluation of the six stress components of every cell:
+density hand-over (device-resident, borrowed) and the five passes of the
+zero-padded FFT convolution with the plan's kernel spectrum. The plan (kernel
+coefficients and their FP64 transform) is built once per geometry before the
+timed region, as the method prescribes (Sec. 2.3).
+
+Default workload: a 128 x 128 x 32 disk of mixed dislocations (t = e_z,
+per-cell random in-plane angle, b = (cos phi, sin phi, 1)/sqrt 2), cells
+dx = dy = 1, dz = 2, radial Gaussian density with 10 % noise; FP32 transforms
+with an FP64 kernel precompute, compared with the plain FP64 path.
+
+Prints one JSON line. ``--gpus`` above 1 is rejected: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid cells/s full σ_ij eval, FP32-batched vs FP64 plain at 1e-5 err; p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def make_workload(name):
+    from paper_1804_01830_amd import workloads as W
+    if name == "disk-mixed-128":
+        return W.disk_mixed()
+    if name == "disk-edge-32":
+        return W.disk_edge()
+    if name == "poly-256":
+        return W.poly_layer()
+    if name == "sweep-64":
+        return W.poly_sweep()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def z_pass_bytes(info, n, C, B, elem):
+    """Algorithmic HBM bytes of one fused z launch: per (kx, ky) column it
+    reads the C*B density columns (Nz complex values each), the 6*C kernel
+    spectrum values of the column (Pz reals each) once, and writes 6*B stress
+    columns (Nz complex each); there are (Px/2 + 1) * Py columns."""
+    Px, Py, Pz = info.padded
+    Nz = n[2]
+    cols = (Px // 2 + 1) * Py
+    per_col = elem * (2 * C * B * Nz + 6 * C * Pz + 2 * 6 * B * Nz)
+    return cols * per_col
+
+
+def path_bytes(info, n, C, B, elem):
+    """Algorithmic HBM bytes of the whole five-pass path for one call."""
+    Px, Py, Pz = info.padded
+    Nx, Ny, Nz = n
+    M1 = Px // 2 + 1
+    cx = 2 * M1                       # reals per complex x-spectrum row
+    xf = elem * B * C * Nz * Ny * (Nx + cx)
+    yf = elem * B * C * Nz * M1 * 2 * (Ny + Py)
+    z = z_pass_bytes(info, n, C, B, elem)
+    yi = elem * B * 6 * Nz * M1 * 2 * (Py + Ny)
+    xi = elem * B * 6 * Nz * Ny * (cx + Nx)
+    return xf + yf + z + yi + xi
+
+
+def time_path(plan, rho, out, steps, warmup, profile):
+    import torch
+    from paper_1804_01830_amd import binding as Bd
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.set_density(rho, Bd.DEVICE_BORROW)
+        plan.stress(out)
+    torch.cuda.synchronize()
+    if profile:
+        plan.set_profiling(True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record(stream)
+        plan.set_density(rho, Bd.DEVICE_BORROW)
+        plan.stress(out)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
+    passes, calls = plan.pass_times() if profile else ({}, 0)
+    if profile:
+        plan.set_profiling(False)
+    return wall, per, passes, calls
+
+
+def pct(sorted_vals, q):
+    k = min(len(sorted_vals) - 1, max(0, int(round(q / 100.0 * (len(sorted_vals) - 1)))))
+    return sorted_vals[k]
+
+
+def _oracle_targets(args):
+    rho, d, lines, mu, nu, tg = args
+    from oracle import stress_direct
+    return stress_direct(rho, d, lines, mu, nu, targets=tg)
+
+
+def rel_l2_targets(got, ref):
+    """Relative L2 error per Voigt component over the sampled cells (a
+    component with a negligible reference norm is measured against the whole
+    norm) and over the whole tensor."""
+    import numpy as np
+    whole = np.linalg.norm(ref)
+    comp = [np.linalg.norm(got[v] - ref[v]) / max(np.linalg.norm(ref[v]), 1e-3 * whole) for v in range(6)]
+    return comp, np.linalg.norm(got - ref) / whole
+
+
+def cpu_baseline(w, seconds):
+    """Time the FP64 oracle (direct sum over all cells) on a bounded sample of
+    target cells on the host cores. Runs before the GPU is touched (the worker
+    pool forks). Returns the baseline record, the targets and their values."""
+    import multiprocessing as mp
+    import numpy as np
+    nx, ny, nz = w["n"]
+    rng = np.random.default_rng(12345)
+    cores = max(1, min(16, os.cpu_count() or 1))
+    # calibrate: one target on one core
+    tg0 = np.array([[nx // 2, ny // 2, nz // 2]])
+    t = time.perf_counter()
+    _oracle_targets((w["rho"][0], w["d"], w["lines"], w["mu"], w["nu"], tg0))
+    one = time.perf_counter() - t
+    n_tg = int(max(cores, min(512, seconds * cores / max(one, 1e-3))))
+    n_tg = max(cores, (n_tg // cores) * cores)
+    tg = np.stack([rng.integers(0, nx, n_tg), rng.integers(0, ny, n_tg), rng.integers(0, nz, n_tg)], axis=1)
+    chunks = np.array_split(tg, cores)
+    ctx = mp.get_context("fork")
+    t = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        parts = pool.map(_oracle_targets, [(w["rho"][0], w["d"], w["lines"], w["mu"], w["nu"], c) for c in chunks])
+    el = time.perf_counter() - t
+    ref = np.concatenate(parts, axis=1)
+    base = {"value": round(n_tg / el, 3), "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_tg} random target cells of the {nx}x{ny}x{nz} grid, each a full FP64 direct sum "
+                      f"over all {nx * ny * nz} source cells (Eq. 10), {cores} worker processes, {el:.1f} s"}
+    return base, tg, ref
+
+
+def errors_at(tg, ref, gpu32, gpu64):
+    sel32 = gpu32[:, tg[:, 2], tg[:, 1], tg[:, 0]]
+    sel64 = gpu64[:, tg[:, 2], tg[:, 1], tg[:, 0]]
+    e32, w32 = rel_l2_targets(sel32, ref)
+    e64, w64 = rel_l2_targets(sel64, ref)
+    return {"fp32_rel_l2_per_component": [float("%.3e" % x) for x in e32], "fp32_rel_l2": float("%.3e" % w32),
+            "fp64_rel_l2_per_component": [float("%.3e" % x) for x in e64], "fp64_rel_l2": float("%.3e" % w64),
+            "targets": int(len(tg))}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="disk-mixed-128")
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the stress evaluation of one grid (or one batch of grids) "
+              "is not sharded across GPUs in this build; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    w = make_workload(args.workload)
+    rho_np = w["rho"]
+    B, C = rho_np.shape[0], rho_np.shape[1]
+    nx, ny, nz = w["n"]
+    cells = B * nx * ny * nz
+    print(f"[bench] workload {w['name']} B={B} C={C} cells={cells}", file=sys.stderr, flush=True)
+    base = None
+    if not args.no_cpu_baseline and B == 1:
+        base, tg, ref = cpu_baseline(w, args.cpu_seconds)
+        print(f"[bench] cpu baseline: {base['sample']}", file=sys.stderr, flush=True)
+
+    import torch
+    from paper_1804_01830_amd import binding as Bd
+    torch.cuda.set_device(0)
+
+    res = {}
+    for prec in (32, 64):
+        desc = Bd.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=prec, batch=B)
+        t = time.perf_counter()
+        plan = Bd.Plan(desc)
+        plan_s = time.perf_counter() - t
+        dt = torch.float32 if prec == 32 else torch.float64
+        rho = torch.from_numpy(rho_np).to("cuda", dtype=dt).contiguous()
+        out = plan.new_output()
+        steps = args.steps if prec == 32 else (args.fp64_steps or max(10, args.steps // 2))
+        wall, per, passes, calls = time_path(plan, rho, out, steps, args.warmup, profile=True)
+        info = plan.info()
+        res[prec] = dict(plan=plan, info=info, wall=wall, per=per, passes=passes, calls=calls, steps=steps,
+                         plan_s=plan_s, out=out[0].double().cpu().numpy() if B == 1 else None)
+        print(f"[bench] precision {prec}: {wall / steps * 1e3:.4f} ms/step, plan {plan_s:.2f} s, "
+              f"passes(ms/call) " + ", ".join(f"{k}={v / max(calls, 1):.4f}" for k, v in passes.items()),
+              file=sys.stderr, flush=True)
+
+    r32, r64 = res[32], res[64]
+    ms32 = r32["wall"] / r32["steps"] * 1e3
+    ms64 = r64["wall"] / r64["steps"] * 1e3
+    value = cells / (ms32 * 1e-3)
+    value64 = cells / (ms64 * 1e-3)
+    elem = 4
+    zbytes = z_pass_bytes(r32["info"], w["n"], C, B, elem)
+    z_ms = r32["passes"]["z_fused"] / max(r32["calls"], 1)
+    achieved = zbytes / (z_ms * 1e-3) / 1e9
+    pbytes = path_bytes(r32["info"], w["n"], C, B, elem)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_z_fused (forward z FFT + 6xC contraction + inverse z)",
+                "algorithmic_bytes_per_launch": int(zbytes), "avg_launch_ms": round(z_ms, 5)}
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "cells/s", "n_gpus": 1,
+        "steps": r32["steps"], "warmup": args.warmup, "ms_per_step": round(ms32, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded)",
+        "config": {"workload": w["name"], "grid": list(w["n"]), "cell": list(w["d"]), "channels": C,
+                   "batch": B, "cells_per_step": cells, "precision": "fp32 transforms and contraction, "
+                   "fp64 kernel coefficients and transform", "parallelism": "single GPU"},
+        "p50_ms": round(pct(r32["per"], 50), 5), "p99_ms": round(pct(r32["per"], 99), 5),
+        "fp64_plain": {"value": round(value64, 1), "ms_per_step": round(ms64, 5), "steps": r64["steps"],
+                       "p50_ms": round(pct(r64["per"], 50), 5), "p99_ms": round(pct(r64["per"], 99), 5)},
+        "speedup_fp32_vs_fp64": round(ms64 / ms32, 3),
+        "pass_ms": {k: round(v / max(r32["calls"], 1), 5) for k, v in r32["passes"].items()},
+        "path_algorithmic_gbs": round(pbytes / (ms32 * 1e-3) / 1e9, 1),
+        "plan_build_s": {"fp32": round(r32["plan_s"], 3), "fp64": round(r64["plan_s"], 3)},
+        "roofline": roofline,
+    }
+    if base is not None:
+        line["cpu_baseline"] = base
+        line["error_vs_oracle"] = errors_at(tg, ref, r32["out"], r64["out"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -133,8 +133,35 @@ ddstress_status ddstress_set_density(ddstress_plan plan, const void* rho, int32_
  * DDSTRESS_E_STATE if no density was set. */
 ddstress_status ddstress_stress(ddstress_plan plan, void* sigma, int32_t where, void* stream);
 
+/* A second plan of the same geometry (grid, cells, constants, lines,
+ * precision, near shells) for `batch` realisations, with its own work buffers
+ * and the kernel spectrum of `src` shared, not copied: the spectrum stays
+ * alive until the last plan sharing it is destroyed. No device work; plans
+ * sharing a spectrum may run concurrently on distinct streams. */
+ddstress_status ddstress_plan_share(ddstress_plan src, int32_t batch, ddstress_plan* out);
+
+/* One-shot evaluation of the first `nbatch` (1 <= nbatch <= batch) densities:
+ * `rho` [nbatch][C][Nz][Ny][Nx] and `sigma` [nbatch][6][Nz][Ny][Nx] are device
+ * buffers in the plan precision. Enqueued on `stream`; the plan's
+ * set_density state is neither used nor changed. The result of a realisation
+ * does not depend on nbatch or on its position in the batch (every
+ * realisation goes through the same arithmetic in the same order). */
+ddstress_status ddstress_stress_batch(ddstress_plan plan, const void* rho, void* sigma, int32_t nbatch,
+                                      void* stream);
+
 /* Facts about a plan (see ddstress_info). */
 ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info);
+
+/* Per-pass timing with HIP events recorded on the stream of each stress()
+ * call: enable != 0 switches it on (and clears the totals), 0 switches it off.
+ * The five passes are, in order: x real-to-complex, y forward, fused z
+ * (forward z + contraction + inverse z), y inverse, x complex-to-real. */
+ddstress_status ddstress_plan_set_profiling(ddstress_plan plan, int32_t enable);
+
+/* Accumulated device milliseconds of each pass over the stress() calls made
+ * since profiling was enabled, and the number of those calls. Synchronises
+ * the recorded events; call it after the stream work has been issued. */
+ddstress_status ddstress_plan_get_pass_times(ddstress_plan plan, double ms[5], int64_t* calls);
 
 /* Free a plan and its device memory (synchronises the device first). NULL is
  * accepted. */

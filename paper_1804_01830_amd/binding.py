@@ -17,8 +17,9 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STAT
 
 # names exported by the library, in header order
 EXPORTS = ("ddstress_plan_footprint", "ddstress_plan_create", "ddstress_set_density", "ddstress_stress",
-           "ddstress_plan_get_info", "ddstress_plan_destroy", "ddstress_kernel_realspace",
-           "ddstress_last_error", "ddstress_version")
+           "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_get_pass_times",
+           "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_last_error", "ddstress_version")
+PASS_NAMES = ("x_r2c", "y_fwd", "z_fused", "y_inv", "x_c2r")
 
 
 class Desc(ctypes.Structure):
@@ -62,8 +63,13 @@ def load(path=LIB_PATH):
     lib.ddstress_plan_get_info.argtypes = [P, ctypes.POINTER(Info)]
     lib.ddstress_plan_destroy.argtypes = [P]
     lib.ddstress_kernel_realspace.argtypes = [ctypes.POINTER(Desc), ctypes.c_int32, P, P]
+    lib.ddstress_plan_set_profiling.argtypes = [P, ctypes.c_int32]
+    lib.ddstress_plan_share.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
+    lib.ddstress_stress_batch.argtypes = [P, P, P, ctypes.c_int32, P]
+    lib.ddstress_plan_get_pass_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in ("ddstress_plan_footprint", "ddstress_plan_create", "ddstress_set_density", "ddstress_stress",
-                 "ddstress_plan_get_info", "ddstress_plan_destroy", "ddstress_kernel_realspace"):
+                 "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_get_pass_times",
+                 "ddstress_plan_destroy", "ddstress_kernel_realspace"):
         getattr(lib, name).restype = ctypes.c_int
     lib.ddstress_last_error.restype = ctypes.c_char_p
     lib.ddstress_last_error.argtypes = []
@@ -114,10 +120,13 @@ class Plan:
     """Owns one ``ddstress_plan``. Tensors are torch CUDA tensors of the plan
     precision; ``stream`` is a torch stream (default: the current stream)."""
 
-    def __init__(self, desc, stream=None):
+    def __init__(self, desc, stream=None, _handle=None):
         self.desc = desc
         self._h = ctypes.c_void_p()
-        check(load().ddstress_plan_create(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(self._h)))
+        if _handle is None:
+            check(load().ddstress_plan_create(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(self._h)))
+        else:
+            self._h = _handle
         self.n = tuple(desc.n)
         self.channels = 3 * desc.n_lines
         self.batch = desc.batch
@@ -144,6 +153,25 @@ class Plan:
                                      _stream_handle(stream)))
         return sigma
 
+    def share(self, batch):
+        """A plan of the same geometry with ``batch`` realisations and its own
+        work buffers, sharing this plan's kernel spectrum."""
+        h = ctypes.c_void_p()
+        check(load().ddstress_plan_share(self._h, int(batch), ctypes.byref(h)))
+        desc = Desc.from_buffer_copy(self.desc)
+        desc.batch = int(batch)
+        return Plan(desc, _handle=h)
+
+    def stress_batch(self, rho, sigma, nbatch, stream=None):
+        """Evaluate the first ``nbatch`` realisations of the device tensors
+        ``rho`` (nbatch, C, Nz, Ny, Nx) and ``sigma`` (nbatch, 6, Nz, Ny, Nx)."""
+        self._check_tensor(rho, (nbatch, self.channels))
+        self._check_tensor(sigma, (nbatch, 6))
+        check(load().ddstress_stress_batch(self._h, ctypes.c_void_p(rho.data_ptr()),
+                                           ctypes.c_void_p(sigma.data_ptr()), int(nbatch),
+                                           _stream_handle(stream)))
+        return sigma
+
     def new_output(self):
         import torch
         dt = torch.float32 if self.precision == 32 else torch.float64
@@ -157,6 +185,16 @@ class Plan:
         if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or tuple(t.shape) != (*lead, nz, ny, nx):
             raise ValueError(f"expected a contiguous CUDA {dt} tensor of shape {(*lead, nz, ny, nx)}, "
                              f"got {tuple(t.shape)} {t.dtype} on {t.device}")
+
+    def set_profiling(self, enable=True):
+        check(load().ddstress_plan_set_profiling(self._h, 1 if enable else 0))
+
+    def pass_times(self):
+        """(dict pass name -> total ms, number of timed stress calls)."""
+        ms = (ctypes.c_double * 5)()
+        calls = ctypes.c_int64()
+        check(load().ddstress_plan_get_pass_times(self._h, ms, ctypes.byref(calls)))
+        return dict(zip(PASS_NAMES, list(ms))), calls.value
 
     def close(self):
         if self._h:

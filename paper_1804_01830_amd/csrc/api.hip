@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -154,8 +155,8 @@ using namespace dds;
 struct ddstress_plan_s {
     ddstress_desc desc;
     Shape shape;
-    DevBuf spec;        // kernel spectrum, plan precision
-    DevBuf tw;          // twiddles, plan precision
+    std::shared_ptr<DevBuf> spec;   // kernel spectrum, plan precision (shared by plans of one geometry)
+    std::shared_ptr<DevBuf> tw;     // twiddles, plan precision
     DevBuf work1, work2;
     DevBuf rho_own;     // density copy (HOST / DEVICE_COPY)
     DevBuf sigma_tmp;   // stress staging for HOST output
@@ -163,6 +164,36 @@ struct ddstress_plan_s {
     bool have_density = false;
     int rows_x = 1, tk_y = 1;
     double re_max = 0.0, im_max = 0.0;
+    // per-pass event timing: events are pooled and reused between folds
+    bool profiling = false;
+    std::vector<hipEvent_t> events;    // 6 per recorded call
+    size_t ev_used = 0;
+    double pass_ms[5] = {0, 0, 0, 0, 0};
+    int64_t timed_calls = 0;
+    ~ddstress_plan_s() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+    void mark(hipStream_t st) {
+        if (!profiling) return;
+        if (ev_used == events.size()) {
+            hipEvent_t e;
+            check_hip(hipEventCreate(&e), "event create");
+            events.push_back(e);
+        }
+        check_hip(hipEventRecord(events[ev_used++], st), "event record");
+    }
+    void fold_events() {
+        for (size_t i = 0; i + 5 < ev_used; i += 6) {
+            check_hip(hipEventSynchronize(events[i + 5]), "event sync");
+            for (int k = 0; k < 5; ++k) {
+                float ms = 0.f;
+                check_hip(hipEventElapsedTime(&ms, events[i + k], events[i + k + 1]), "event time");
+                pass_ms[k] += ms;
+            }
+            ++timed_calls;
+        }
+        ev_used = 0;
+    }
 };
 
 namespace {
@@ -213,7 +244,7 @@ void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
         gz.ios = gz.oos = s.wx;
         gz.ips = gz.ops = plane_c;
         launch_col_fft<double>(s.P[2], true, kc.as<cplx<double>>(), kc.as<cplx<double>>(), gz, tw, tkz, st);
-        launch_extract<T>(kc.as<cplx<double>>(), p->spec.as<T>(), l, s.C, s.M1, s.wx, s.P[1], s.P[2], s.tkz,
+        launch_extract<T>(kc.as<cplx<double>>(), p->spec->as<T>(), l, s.C, s.M1, s.wx, s.P[1], s.P[2], s.tkz,
                           s.ntz, inv_p, maxbits.as<unsigned long long>(), st);
     }
     unsigned long long bits[2] = {0, 0};
@@ -230,23 +261,25 @@ template <typename T>
 void upload_twiddles(ddstress_plan_s* p, hipStream_t st) {
     std::vector<cplx<T>> host(kTwiddleEntries);
     fill_twiddles<T>(host.data());
-    check_hip(hipMemcpyAsync(p->tw.p, host.data(), host.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, st),
+    check_hip(hipMemcpyAsync(p->tw->p, host.data(), host.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, st),
               "twiddle upload");
     check_hip(hipStreamSynchronize(st), "twiddle upload");
 }
 
 template <typename T>
-void run_stress(ddstress_plan_s* p, T* sigma, hipStream_t st) {
-    const Shape& s = p->shape;
-    const T* rho = static_cast<const T*>(p->rho);
+void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t st) {
+    Shape s = p->shape;
+    s.B = nb;       // realisations evaluated by this call (<= the plan's batch)
     cplx<T>* w1 = p->work1.as<cplx<T>>();
     cplx<T>* w2 = p->work2.as<cplx<T>>();
-    const cplx<T>* tw = p->tw.as<cplx<T>>();
+    const cplx<T>* tw = p->tw->as<cplx<T>>();
     const int64_t BC = (int64_t)s.B * s.C;
     const int64_t B6 = (int64_t)s.B * 6;
     const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2], Py = s.P[1];
+    p->mark(st);
     // x forward: rows (b, c, z, y) of Nx reals -> M+1 complex
     launch_x_r2c<T>(s.M, rho, w1, BC * Nz * Ny, Nx, Nx, s.wx, tw, p->rows_x, st);
+    p->mark(st);
     // y forward: Ny rows -> Py rows
     ColGeom gy{};
     gy.ncols = s.M1;
@@ -259,6 +292,7 @@ void run_stress(ddstress_plan_s* p, T* sigma, hipStream_t st) {
     gy.ors = s.wx;
     gy.ops = (int64_t)Py * s.wx;
     launch_col_fft<T>(Py, true, w1, w2, gy, tw, p->tk_y, st);
+    p->mark(st);
     // z forward + contraction + z inverse
     ZGeom gz{};
     gz.ncols = s.M1;
@@ -273,7 +307,8 @@ void run_stress(ddstress_plan_s* p, T* sigma, hipStream_t st) {
     gz.ors = gz.irs;
     gz.oqs = gz.iqs;
     gz.oos = gz.ios;
-    launch_z_fused<T>(s.P[2], w2, w1, p->spec.as<T>(), gz, tw, s.tkz, st);
+    launch_z_fused<T>(s.P[2], w2, w1, p->spec->as<T>(), gz, tw, s.tkz, st);
+    p->mark(st);
     // y inverse: Py rows -> Ny rows
     ColGeom gi{};
     gi.ncols = s.M1;
@@ -286,8 +321,10 @@ void run_stress(ddstress_plan_s* p, T* sigma, hipStream_t st) {
     gi.ors = s.wx;
     gi.ops = (int64_t)Ny * s.wx;
     launch_col_fft<T>(Py, false, w1, w2, gi, tw, p->tk_y, st);
+    p->mark(st);
     // x inverse: rows (b, v, z, y) -> Nx reals
     launch_x_c2r<T>(s.M, w2, sigma, B6 * Nz * Ny, Nx, s.wx, Nx, tw, p->rows_x, st);
+    p->mark(st);
 }
 
 void create_plan(const ddstress_desc* desc, hipStream_t st, ddstress_plan* out) {
@@ -301,8 +338,10 @@ void create_plan(const ddstress_desc* desc, hipStream_t st, ddstress_plan* out) 
         const Shape& s = p->shape;
         p->rows_x = default_rows(s.M, s.elem);
         p->tk_y = default_col_tk(s.P[1], s.elem);
-        p->spec.alloc(spec_bytes(s), "kernel spectrum");
-        p->tw.alloc(twiddle_bytes(s), "twiddles");
+        p->spec = std::make_shared<DevBuf>();
+        p->tw = std::make_shared<DevBuf>();
+        p->spec->alloc(spec_bytes(s), "kernel spectrum");
+        p->tw->alloc(twiddle_bytes(s), "twiddles");
         p->work1.alloc((size_t)work1_elems(s) * 2 * s.elem, "work buffer 1");
         p->work2.alloc((size_t)work2_elems(s) * 2 * s.elem, "work buffer 2");
         if (s.elem == 4) {
@@ -375,11 +414,53 @@ ddstress_status ddstress_stress(ddstress_plan plan, void* sigma, int32_t where, 
             dst = plan->sigma_tmp.p;
         }
         if (plan->shape.elem == 4)
-            run_stress<float>(plan, static_cast<float*>(dst), st);
+            run_stress<float>(plan, static_cast<const float*>(plan->rho), static_cast<float*>(dst), plan->shape.B, st);
         else
-            run_stress<double>(plan, static_cast<double*>(dst), st);
+            run_stress<double>(plan, static_cast<const double*>(plan->rho), static_cast<double*>(dst), plan->shape.B,
+                               st);
         if (where == DDSTRESS_HOST)
             check_hip(hipMemcpyAsync(sigma, dst, bytes, hipMemcpyDeviceToHost, st), "stress copy to host");
+    });
+}
+
+ddstress_status ddstress_plan_share(ddstress_plan src, int32_t batch, ddstress_plan* out) {
+    return guarded([&] {
+        if (!src || !out) fail(DDSTRESS_E_INVALID, "NULL argument");
+        if (batch < 1) fail(DDSTRESS_E_INVALID, "batch must be >= 1");
+        *out = nullptr;
+        auto* p = new ddstress_plan_s();
+        try {
+            p->desc = src->desc;
+            p->desc.batch = batch;
+            p->shape = make_shape(&p->desc);
+            p->spec = src->spec;
+            p->tw = src->tw;
+            p->rows_x = src->rows_x;
+            p->tk_y = src->tk_y;
+            p->re_max = src->re_max;
+            p->im_max = src->im_max;
+            const Shape& s = p->shape;
+            p->work1.alloc((size_t)work1_elems(s) * 2 * s.elem, "work buffer 1");
+            p->work2.alloc((size_t)work2_elems(s) * 2 * s.elem, "work buffer 2");
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+    });
+}
+
+ddstress_status ddstress_stress_batch(ddstress_plan plan, const void* rho, void* sigma, int32_t nbatch,
+                                      void* stream) {
+    return guarded([&] {
+        if (!plan) fail(DDSTRESS_E_INVALID, "plan is NULL");
+        if (!rho || !sigma) fail(DDSTRESS_E_INVALID, "NULL buffer");
+        if (nbatch < 1 || nbatch > plan->shape.B) fail(DDSTRESS_E_INVALID, "nbatch must lie in [1, batch]");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (plan->shape.elem == 4)
+            run_stress<float>(plan, static_cast<const float*>(rho), static_cast<float*>(sigma), nbatch, st);
+        else
+            run_stress<double>(plan, static_cast<const double*>(rho), static_cast<double*>(sigma), nbatch, st);
     });
 }
 
@@ -397,10 +478,29 @@ ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info) 
         info->batch = s.B;
         info->precision = plan->desc.precision;
         info->tile_z = s.tkz;
-        info->cached_bytes = plan->spec.bytes + plan->tw.bytes;
+        info->cached_bytes = plan->spec->bytes + plan->tw->bytes;
         info->work_bytes = plan->work1.bytes + plan->work2.bytes + plan->rho_own.bytes + plan->sigma_tmp.bytes;
         info->kernel_real_max = plan->re_max;
         info->kernel_imag_max = plan->im_max;
+    });
+}
+
+ddstress_status ddstress_plan_set_profiling(ddstress_plan plan, int32_t enable) {
+    return guarded([&] {
+        if (!plan) fail(DDSTRESS_E_INVALID, "plan is NULL");
+        plan->ev_used = 0;
+        plan->profiling = enable != 0;
+        for (double& v : plan->pass_ms) v = 0.0;
+        plan->timed_calls = 0;
+    });
+}
+
+ddstress_status ddstress_plan_get_pass_times(ddstress_plan plan, double ms[5], int64_t* calls) {
+    return guarded([&] {
+        if (!plan || !ms) fail(DDSTRESS_E_INVALID, "NULL argument");
+        plan->fold_events();
+        for (int k = 0; k < 5; ++k) ms[k] = plan->pass_ms[k];
+        if (calls) *calls = plan->timed_calls;
     });
 }
 

@@ -132,3 +132,41 @@ def test_stress_before_density_is_a_state_error():
         plan.stress(out)
     assert e.value.status == B.E_STATE
     plan.close()
+
+
+def _load_golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name + ".json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_poly_layer_256_golden(precision):
+    """Full-size 256 x 256 x 64 polycrystal layer (two line directions,
+    C = 6) against stored oracle values at 10 cells."""
+    g = _load_golden("poly_layer_256x256x64")
+    w = W.poly_layer()
+    assert list(w["n"]) == g["n"] and np.allclose(w["lines"], g["lines"])
+    tg = np.array(g["targets"])
+    ref = np.array(g["sigma_voigt"]).T
+    got = gpu_stress(w, precision)[0][:, tg[:, 2], tg[:, 1], tg[:, 0]]
+    comp, whole = rel_l2(got, ref)
+    _say(f"[poly-layer-256] precision={precision} per component {np.array2string(comp, precision=2)} "
+         f"whole {whole:.2e}")
+    assert np.all(comp <= TOL[precision]) and whole <= TOL[precision]
+
+
+def test_poly_sweep_batch64_golden():
+    """The 64-realisation batch on one plan (B = 64, FP32): realisations 0
+    and 63 against stored oracle values."""
+    w = W.poly_sweep()
+    got = gpu_stress(w, 32)
+    for name in ("poly_sweep_128x128x32_b0", "poly_sweep_128x128x32_b63"):
+        g = _load_golden(name)
+        tg = np.array(g["targets"])
+        ref = np.array(g["sigma_voigt"]).T
+        sel = got[g["batch_index"]][:, tg[:, 2], tg[:, 1], tg[:, 0]]
+        comp, whole = rel_l2(sel, ref)
+        _say(f"[{name}] per component {np.array2string(comp, precision=2)} whole {whole:.2e}")
+        assert np.all(comp <= TOL[32]) and whole <= TOL[32]
