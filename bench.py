@@ -67,10 +67,11 @@ def path_bytes(info, n, C, B, elem):
     return xf + yf + z + yi + xi
 
 
-def time_path(plan, rho, out, steps, warmup, profile):
+def time_path(plan, rho, out, steps, warmup, profile, graph=False):
     import torch
     from paper_1804_01830_amd import binding as Bd
     stream = torch.cuda.current_stream()
+    plan.set_graph(graph)
     for _ in range(warmup):
         plan.set_density(rho, Bd.DEVICE_BORROW)
         plan.stress(out)
@@ -92,6 +93,7 @@ def time_path(plan, rho, out, steps, warmup, profile):
     passes, calls = plan.pass_times() if profile else ({}, 0)
     if profile:
         plan.set_profiling(False)
+    plan.set_graph(False)
     return wall, per, passes, calls
 
 
@@ -156,6 +158,66 @@ def errors_at(tg, ref, gpu32, gpu64):
             "targets": int(len(tg))}
 
 
+SERVE_SHAPES = ((64, 64, 64), (128, 128, 32), (256, 256, 64), (256, 256, 128))
+
+
+def serve_bench(args):
+    """Serving stream: Poisson arrivals of stress requests on grids drawn from
+    SERVE_SHAPES with polycrystal densities (grain size 16 cells), admitted by
+    HBM footprint, batched per shape; reports p50/p99 latency and cells/s at
+    the saturated rate and at a fraction of it."""
+    import numpy as np
+    import torch
+    from paper_1804_01830_amd import workloads as W
+    from paper_1804_01830_amd.serving import GpuExecutor, Request, Server, ShapeKey, poisson_arrivals
+    torch.cuda.set_device(0)
+    pools, keys = [], []
+    for n in SERVE_SHAPES:
+        w = W.poly_layer(*n, batch_seeds=list(range(args.serve_pool)))
+        keys.append(ShapeKey(n=tuple(n), d=tuple(w["d"]), mu=w["mu"], nu=w["nu"],
+                             lines=tuple(tuple(map(float, t)) for t in w["lines"]), precision=32))
+        pools.append(torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32))
+        print(f"[serve] pool {n}: {args.serve_pool} densities", file=sys.stderr, flush=True)
+    ex = GpuExecutor(use_graph=True, tune=not args.no_tune)
+    srv = Server(ex, hbm_budget=int(args.serve_budget_gb * (1 << 30)), max_batch=args.serve_batch,
+                 max_slots_per_shape=2)
+    rng = np.random.default_rng(5)
+
+    def make(count, rate):
+        arr = np.zeros(count) if rate is None else poisson_arrivals(rate, count, seed=5)
+        t0 = ex.clock()
+        out = []
+        for i, t in enumerate(arr):
+            s = int(rng.integers(len(keys)))
+            out.append(Request(i, keys[s], rho=pools[s][int(rng.integers(args.serve_pool))], arrival=t0 + float(t)))
+        return out
+
+    # warm-up: one request per shape builds the plans (and tunings)
+    srv.run([Request(i, k, rho=pools[i][0], arrival=ex.clock()) for i, k in enumerate(keys)], ex.clock)
+    torch.cuda.synchronize()
+    results = {}
+    srv.completed, srv.batches = [], []
+    sat = srv.run(make(args.serve_requests, None), ex.clock)
+    torch.cuda.synchronize()
+    results["saturated"] = sat
+    rate_sat = sat["requests"] / sat["makespan_s"]
+    for frac in (0.5, 0.9):
+        srv.completed, srv.batches = [], []
+        st = srv.run(make(args.serve_requests, frac * rate_sat), ex.clock)
+        torch.cuda.synchronize()
+        st["offered_rate_per_s"] = frac * rate_sat
+        results[f"{frac:.2f}x"] = st
+    line = {"metric": "served stress requests: p50/p99 latency and cells/s", "unit": "cells/s",
+            "value": round(sat["cells_per_s"], 1), "higher_is_better": True, "n_gpus": 1, "dtype": "f32",
+            "data": "synthetic (seeded)",
+            "config": {"workload": "serve-poly-mix", "shapes": [list(n) for n in SERVE_SHAPES],
+                       "max_batch": args.serve_batch, "hbm_budget_gb": args.serve_budget_gb,
+                       "requests_per_run": args.serve_requests},
+            "runs": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                     for k, v in results.items()}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,11 +227,20 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shapes for the FP32 plan")
+    ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-pool", type=int, default=4)
+    ap.add_argument("--serve-batch", type=int, default=4)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the stress evaluation of one grid (or one batch of grids) "
               "is not sharded across GPUs in this build; use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.serve:
+        serve_bench(args)
+        return
 
     w = make_workload(args.workload)
     rho_np = w["rho"]
@@ -186,23 +257,35 @@ def main():
     from paper_1804_01830_amd import binding as Bd
     torch.cuda.set_device(0)
 
+    from paper_1804_01830_amd import tuning as Tn
     res = {}
     for prec in (32, 64):
         desc = Bd.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=prec, batch=B)
         t = time.perf_counter()
-        plan = Bd.Plan(desc)
+        tune = None
+        if prec == 32 and not args.no_tune:
+            tune = Tn.get_tuning(desc)
+        plan = Bd.Plan(desc, tuning=tune)
         plan_s = time.perf_counter() - t
         dt = torch.float32 if prec == 32 else torch.float64
         rho = torch.from_numpy(rho_np).to("cuda", dtype=dt).contiguous()
         out = plan.new_output()
         steps = args.steps if prec == 32 else (args.fp64_steps or max(10, args.steps // 2))
         wall, per, passes, calls = time_path(plan, rho, out, steps, args.warmup, profile=True)
+        graph = None
+        if prec == 32:
+            gw, gper, _, _ = time_path(plan, rho, out, steps, args.warmup, profile=False, graph=True)
+            graph = dict(wall=gw, per=gper)
         info = plan.info()
         res[prec] = dict(plan=plan, info=info, wall=wall, per=per, passes=passes, calls=calls, steps=steps,
-                         plan_s=plan_s, out=out[0].double().cpu().numpy() if B == 1 else None)
+                         plan_s=plan_s, graph=graph, tune=Tn.to_dict(tune) if tune is not None else None,
+                         out=out[0].double().cpu().numpy() if B == 1 else None)
         print(f"[bench] precision {prec}: {wall / steps * 1e3:.4f} ms/step, plan {plan_s:.2f} s, "
               f"passes(ms/call) " + ", ".join(f"{k}={v / max(calls, 1):.4f}" for k, v in passes.items()),
               file=sys.stderr, flush=True)
+        if graph:
+            print(f"[bench] precision {prec} graph replay: {graph['wall'] / steps * 1e3:.4f} ms/step",
+                  file=sys.stderr, flush=True)
 
     r32, r64 = res[32], res[64]
     ms32 = r32["wall"] / r32["steps"] * 1e3
@@ -230,6 +313,11 @@ def main():
         "fp64_plain": {"value": round(value64, 1), "ms_per_step": round(ms64, 5), "steps": r64["steps"],
                        "p50_ms": round(pct(r64["per"], 50), 5), "p99_ms": round(pct(r64["per"], 99), 5)},
         "speedup_fp32_vs_fp64": round(ms64 / ms32, 3),
+        "graph_replay": {"value": round(cells / (r32["graph"]["wall"] / r32["steps"]), 1),
+                         "ms_per_step": round(r32["graph"]["wall"] / r32["steps"] * 1e3, 5),
+                         "p50_ms": round(pct(r32["graph"]["per"], 50), 5),
+                         "p99_ms": round(pct(r32["graph"]["per"], 99), 5)},
+        "tuning": r32["tune"],
         "pass_ms": {k: round(v / max(r32["calls"], 1), 5) for k, v in r32["passes"].items()},
         "path_algorithmic_gbs": round(pbytes / (ms32 * 1e-3) / 1e9, 1),
         "plan_build_s": {"fp32": round(r32["plan_s"], 3), "fp64": round(r64["plan_s"], 3)},

@@ -95,11 +95,22 @@ typedef struct {
     int32_t batch;         /* B */
     int32_t precision;     /* 32 or 64 */
     int32_t tile_z;        /* columns per block of the fused z kernel (fixes the spectrum layout) */
+    int32_t tile_y;        /* columns per block of the y passes */
+    int32_t rows_x;        /* rows per block of the x passes */
     size_t  cached_bytes;  /* device bytes held for the plan's lifetime (kernel spectrum, tables) */
     size_t  work_bytes;    /* device bytes of per-call work buffers */
     double  kernel_real_max;  /* max |Re K^| over the spectrum: zero up to rounding (K is odd) */
     double  kernel_imag_max;  /* max |Im K^| */
 } ddstress_info;
+
+/* Launch shapes of the passes: a tuning choice. Tile choices change which
+ * threads do the work, not the arithmetic: results are bit-identical. */
+typedef struct {
+    int32_t rows_x;        /* rows per block of the x passes (forward and inverse) */
+    int32_t tk_y;          /* consecutive kx columns per block of the y passes */
+    int32_t tk_z;          /* consecutive kx columns per block of the fused z pass */
+    float   ms[3];         /* autotune: median device ms of the chosen x pair, y pair and z pass */
+} ddstress_tuning;
 
 /* Device bytes a plan for `desc` will hold: `cached_bytes` for its lifetime,
  * `work_bytes` for its per-call buffers, `build_bytes` transiently during
@@ -116,6 +127,19 @@ ddstress_status ddstress_plan_footprint(const ddstress_desc* desc, size_t* cache
  * the build has completed (it synchronises the stream). On success *out owns
  * device memory until ddstress_plan_destroy. */
 ddstress_status ddstress_plan_create(const ddstress_desc* desc, void* stream, ddstress_plan* out);
+
+/* Autotuner: times every admissible tile choice of each pass (threads per
+ * block <= 512, LDS <= 64 KiB) on zero-filled buffers of the descriptor's
+ * shape, precision and batch, with HIP events on `stream` (median of five runs
+ * after two warm-up runs), and returns the fastest per pass. Synchronous;
+ * allocates its buffers for the duration of the call. */
+ddstress_status ddstress_autotune(const ddstress_desc* desc, void* stream, ddstress_tuning* out);
+
+/* As ddstress_plan_create, with the launch shapes of `tuning` (for example
+ * from ddstress_autotune). DDSTRESS_E_INVALID if a choice is outside the
+ * limits for this shape. */
+ddstress_status ddstress_plan_create_tuned(const ddstress_desc* desc, const ddstress_tuning* tuning, void* stream,
+                                           ddstress_plan* out);
 
 /* Hand the B densities [B][C][Nz][Ny][Nx] (plan precision) to the plan.
  * HOST and DEVICE_COPY enqueue a copy on `stream` (the caller may reuse rho
@@ -157,6 +181,14 @@ ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info);
  * The five passes are, in order: x real-to-complex, y forward, fused z
  * (forward z + contraction + inverse z), y inverse, x complex-to-real. */
 ddstress_status ddstress_plan_set_profiling(ddstress_plan plan, int32_t enable);
+
+/* Graph replay: with enable != 0, stress() and stress_batch() record their
+ * launch sequence once per (density buffer, stress buffer, nbatch) into a HIP
+ * graph (captured on a private stream, at most 8 kept per plan, least recently
+ * used dropped first) and replay it on the caller's stream; the arithmetic is
+ * the same as with direct launches. 0 switches it off and frees the graphs.
+ * While profiling is on, calls launch directly. */
+ddstress_status ddstress_plan_set_graph(ddstress_plan plan, int32_t enable);
 
 /* Accumulated device milliseconds of each pass over the stress() calls made
  * since profiling was enabled, and the number of those calls. Synchronises

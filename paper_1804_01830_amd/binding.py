@@ -16,8 +16,9 @@ HOST, DEVICE_COPY, DEVICE_BORROW = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STATE", 5: "E_UNSUPPORTED"}
 
 # names exported by the library, in header order
-EXPORTS = ("ddstress_plan_footprint", "ddstress_plan_create", "ddstress_set_density", "ddstress_stress",
-           "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_get_pass_times",
+EXPORTS = ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
+           "ddstress_set_density", "ddstress_stress",
+           "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times",
            "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_last_error", "ddstress_version")
 PASS_NAMES = ("x_r2c", "y_fwd", "z_fused", "y_inv", "x_c2r")
 
@@ -29,9 +30,15 @@ class Desc(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("rows_x", ctypes.c_int32), ("tk_y", ctypes.c_int32), ("tk_z", ctypes.c_int32),
+                ("ms", ctypes.c_float * 3)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("padded", ctypes.c_int32 * 3), ("subdiv", ctypes.c_int32 * 3), ("channels", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("precision", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("rows_x", ctypes.c_int32),
                 ("cached_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t),
                 ("kernel_real_max", ctypes.c_double), ("kernel_imag_max", ctypes.c_double)]
 
@@ -58,17 +65,21 @@ def load(path=LIB_PATH):
     lib.ddstress_plan_footprint.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(S), ctypes.POINTER(S),
                                             ctypes.POINTER(S)]
     lib.ddstress_plan_create.argtypes = [ctypes.POINTER(Desc), P, ctypes.POINTER(P)]
+    lib.ddstress_autotune.argtypes = [ctypes.POINTER(Desc), P, ctypes.POINTER(Tuning)]
+    lib.ddstress_plan_create_tuned.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(Tuning), P, ctypes.POINTER(P)]
     lib.ddstress_set_density.argtypes = [P, P, ctypes.c_int32, P]
     lib.ddstress_stress.argtypes = [P, P, ctypes.c_int32, P]
     lib.ddstress_plan_get_info.argtypes = [P, ctypes.POINTER(Info)]
     lib.ddstress_plan_destroy.argtypes = [P]
     lib.ddstress_kernel_realspace.argtypes = [ctypes.POINTER(Desc), ctypes.c_int32, P, P]
     lib.ddstress_plan_set_profiling.argtypes = [P, ctypes.c_int32]
+    lib.ddstress_plan_set_graph.argtypes = [P, ctypes.c_int32]
     lib.ddstress_plan_share.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
     lib.ddstress_stress_batch.argtypes = [P, P, P, ctypes.c_int32, P]
     lib.ddstress_plan_get_pass_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
-    for name in ("ddstress_plan_footprint", "ddstress_plan_create", "ddstress_set_density", "ddstress_stress",
-                 "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_get_pass_times",
+    for name in ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
+                 "ddstress_set_density", "ddstress_stress",
+                 "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_graph", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times",
                  "ddstress_plan_destroy", "ddstress_kernel_realspace"):
         getattr(lib, name).restype = ctypes.c_int
     lib.ddstress_last_error.restype = ctypes.c_char_p
@@ -120,13 +131,16 @@ class Plan:
     """Owns one ``ddstress_plan``. Tensors are torch CUDA tensors of the plan
     precision; ``stream`` is a torch stream (default: the current stream)."""
 
-    def __init__(self, desc, stream=None, _handle=None):
+    def __init__(self, desc, stream=None, tuning=None, _handle=None):
         self.desc = desc
         self._h = ctypes.c_void_p()
-        if _handle is None:
+        if _handle is not None:
+            self._h = _handle
+        elif tuning is None:
             check(load().ddstress_plan_create(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(self._h)))
         else:
-            self._h = _handle
+            check(load().ddstress_plan_create_tuned(ctypes.byref(desc), ctypes.byref(tuning), _stream_handle(stream),
+                                                    ctypes.byref(self._h)))
         self.n = tuple(desc.n)
         self.channels = 3 * desc.n_lines
         self.batch = desc.batch
@@ -189,6 +203,9 @@ class Plan:
     def set_profiling(self, enable=True):
         check(load().ddstress_plan_set_profiling(self._h, 1 if enable else 0))
 
+    def set_graph(self, enable=True):
+        check(load().ddstress_plan_set_graph(self._h, 1 if enable else 0))
+
     def pass_times(self):
         """(dict pass name -> total ms, number of timed stress calls)."""
         ms = (ctypes.c_double * 5)()
@@ -206,6 +223,13 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def autotune(desc, stream=None):
+    """Time the admissible launch shapes of each pass on the device; returns a Tuning."""
+    t = Tuning()
+    check(load().ddstress_autotune(ctypes.byref(desc), _stream_handle(stream), ctypes.byref(t)))
+    return t
 
 
 def kernel_realspace(desc, line, out, stream=None):

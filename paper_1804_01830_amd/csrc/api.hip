@@ -170,8 +170,25 @@ struct ddstress_plan_s {
     size_t ev_used = 0;
     double pass_ms[5] = {0, 0, 0, 0, 0};
     int64_t timed_calls = 0;
+    // graph replay of the per-call launch sequence, keyed by buffers and batch
+    struct GraphEntry {
+        const void* rho;
+        void* sigma;
+        int nb;
+        hipGraphExec_t exec;
+    };
+    bool use_graph = false;
+    std::vector<GraphEntry> graphs;     // most recently used last
+    hipStream_t cap_stream = nullptr;
+    static constexpr size_t kMaxGraphs = 8;
     ~ddstress_plan_s() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        drop_graphs();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
+    void drop_graphs() {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
     }
     void mark(hipStream_t st) {
         if (!profiling) return;
@@ -327,7 +344,77 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     p->mark(st);
 }
 
-void create_plan(const ddstress_desc* desc, hipStream_t st, ddstress_plan* out) {
+template <typename T>
+void capture_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipGraphExec_t* exec) {
+    if (!p->cap_stream) check_hip(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "capture stream");
+    check_hip(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipGraph_t g = nullptr;
+    try {
+        run_stress<T>(p, rho, sigma, nb, p->cap_stream);
+    } catch (...) {
+        (void)hipStreamEndCapture(p->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    check_hip(hipStreamEndCapture(p->cap_stream, &g), "end capture");
+    hipError_t e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    check_hip(e, "graph instantiate");
+}
+
+// Enqueue one evaluation: a replayed graph when enabled (and not profiling), else direct launches.
+template <typename T>
+void enqueue_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t st) {
+    if (!p->use_graph || p->profiling) {
+        run_stress<T>(p, rho, sigma, nb, st);
+        return;
+    }
+    auto& gs = p->graphs;
+    size_t i = 0;
+    for (; i < gs.size(); ++i)
+        if (gs[i].rho == rho && gs[i].sigma == sigma && gs[i].nb == nb) break;
+    if (i == gs.size()) {
+        if (gs.size() == ddstress_plan_s::kMaxGraphs) {
+            (void)hipGraphExecDestroy(gs.front().exec);
+            gs.erase(gs.begin());
+        }
+        ddstress_plan_s::GraphEntry ge{rho, sigma, nb, nullptr};
+        capture_stress<T>(p, rho, sigma, nb, &ge.exec);
+        gs.push_back(ge);
+        i = gs.size() - 1;
+    } else if (i + 1 != gs.size()) {
+        std::rotate(gs.begin() + i, gs.begin() + i + 1, gs.end());
+        i = gs.size() - 1;
+    }
+    check_hip(hipGraphLaunch(gs[i].exec, st), "graph launch");
+}
+
+// Launch-shape limits shared by the defaults, the autotuner and tuned plans.
+constexpr int kMaxThreads = 512;
+constexpr size_t kMaxLds = 64 * 1024;
+bool rows_ok(const Shape& s, int r) {
+    return r >= 1 && r * (s.M / elems_for(s.M)) <= kMaxThreads && (size_t)r * (s.M + 1) * 2 * s.elem <= kMaxLds;
+}
+bool col_ok(const Shape& s, int N, int tk) {
+    return tk >= 1 && col_threads(N, tk) <= kMaxThreads && (size_t)N * tk * 2 * s.elem <= kMaxLds;
+}
+bool z_ok(const Shape& s, int tk) {
+    return tk >= 1 && z_threads(s.P[2], tk, s.elem) <= kMaxThreads && (size_t)s.P[2] * tk * 2 * s.elem <= kMaxLds;
+}
+
+void apply_tuning(Shape& s, int& rows_x, int& tk_y, const ddstress_tuning* t) {
+    rows_x = default_rows(s.M, s.elem);
+    tk_y = default_col_tk(s.P[1], s.elem);
+    if (!t) return;
+    if (!rows_ok(s, t->rows_x) || !col_ok(s, s.P[1], t->tk_y) || !z_ok(s, t->tk_z))
+        fail(DDSTRESS_E_INVALID, "tuning choice outside the launch limits of this shape");
+    rows_x = t->rows_x;
+    tk_y = t->tk_y;
+    s.tkz = t->tk_z;
+    s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
+}
+
+void create_plan(const ddstress_desc* desc, const ddstress_tuning* tuning, hipStream_t st, ddstress_plan* out) {
     if (!out) fail(DDSTRESS_E_INVALID, "output plan pointer is NULL");
     *out = nullptr;
     validate(desc);
@@ -335,9 +422,8 @@ void create_plan(const ddstress_desc* desc, hipStream_t st, ddstress_plan* out) 
     try {
         p->desc = *desc;
         p->shape = make_shape(desc);
+        apply_tuning(p->shape, p->rows_x, p->tk_y, tuning);
         const Shape& s = p->shape;
-        p->rows_x = default_rows(s.M, s.elem);
-        p->tk_y = default_col_tk(s.P[1], s.elem);
         p->spec = std::make_shared<DevBuf>();
         p->tw = std::make_shared<DevBuf>();
         p->spec->alloc(spec_bytes(s), "kernel spectrum");
@@ -358,6 +444,109 @@ void create_plan(const ddstress_desc* desc, hipStream_t st, ddstress_plan* out) 
     *out = p;
 }
 
+// Median device time of `reps` runs of f on stream st (after two warm-up runs).
+template <class F>
+float time_median(hipStream_t st, int reps, F&& f) {
+    hipEvent_t a, b;
+    check_hip(hipEventCreate(&a), "event create");
+    check_hip(hipEventCreate(&b), "event create");
+    std::vector<float> t;
+    try {
+        for (int i = 0; i < 2; ++i) f();
+        for (int i = 0; i < reps; ++i) {
+            check_hip(hipEventRecord(a, st), "event record");
+            f();
+            check_hip(hipEventRecord(b, st), "event record");
+            check_hip(hipEventSynchronize(b), "event sync");
+            float ms = 0.f;
+            check_hip(hipEventElapsedTime(&ms, a, b), "event time");
+            t.push_back(ms);
+        }
+    } catch (...) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        throw;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+// Time every admissible tile choice of each pass on zero-filled buffers of the
+// plan's shape and keep the fastest. Tile choices do not change the arithmetic.
+template <typename T>
+void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* out) {
+    Shape s = make_shape(desc);
+    const int64_t BC = (int64_t)s.B * s.C, B6 = (int64_t)s.B * 6;
+    const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2], Py = s.P[1], Pz = s.P[2];
+    std::vector<int> tkz_list;
+    for (int tk = 1; tk <= 256; tk *= 2)
+        if (z_ok(s, tk) && z_threads(Pz, tk, s.elem) >= 64) tkz_list.push_back(tk);
+    if (tkz_list.empty()) tkz_list.push_back(s.tkz);
+    size_t spec_max = 0;
+    for (int tk : tkz_list) {
+        Shape t = s;
+        t.tkz = tk;
+        t.ntz = (s.M1 + tk - 1) / tk;
+        spec_max = std::max(spec_max, spec_bytes(t));
+    }
+    DevBuf rho, sig, w1, w2, spec, tw;
+    rho.alloc(density_bytes(s), "tuning density");
+    sig.alloc(sigma_bytes(s), "tuning stress");
+    w1.alloc((size_t)work1_elems(s) * 2 * s.elem, "tuning work 1");
+    w2.alloc((size_t)work2_elems(s) * 2 * s.elem, "tuning work 2");
+    spec.alloc(spec_max, "tuning spectrum");
+    tw.alloc(twiddle_bytes(s), "tuning twiddles");
+    check_hip(hipMemsetAsync(rho.p, 0, rho.bytes, st), "clear");
+    check_hip(hipMemsetAsync(w1.p, 0, w1.bytes, st), "clear");
+    check_hip(hipMemsetAsync(w2.p, 0, w2.bytes, st), "clear");
+    check_hip(hipMemsetAsync(spec.p, 0, spec.bytes, st), "clear");
+    std::vector<cplx<T>> host(kTwiddleEntries);
+    fill_twiddles<T>(host.data());
+    check_hip(hipMemcpyAsync(tw.p, host.data(), host.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, st), "upload");
+    check_hip(hipStreamSynchronize(st), "tuning setup");
+    const cplx<T>* twp = tw.as<cplx<T>>();
+    const int reps = 5;
+
+    float best = 1e30f;
+    for (int r = 1; r <= kMaxThreads; r *= 2) {
+        if (!rows_ok(s, r)) continue;
+        float ms = time_median(st, reps, [&] {
+            launch_x_r2c<T>(s.M, rho.as<T>(), w1.as<cplx<T>>(), BC * Nz * Ny, Nx, Nx, s.wx, twp, r, st);
+            launch_x_c2r<T>(s.M, w2.as<cplx<T>>(), sig.as<T>(), B6 * Nz * Ny, Nx, s.wx, Nx, twp, r, st);
+        });
+        if (ms < best) { best = ms; out->rows_x = r; out->ms[0] = ms; }
+    }
+    best = 1e30f;
+    for (int tk = 1; tk <= 256; tk *= 2) {
+        if (!col_ok(s, Py, tk) || col_threads(Py, tk) < 64) continue;
+        ColGeom gy{};
+        gy.ncols = s.M1; gy.n_in = Ny; gy.n_out = Py; gy.nouter = 1; gy.nplanes = BC * Nz;
+        gy.irs = s.wx; gy.ips = (int64_t)Ny * s.wx; gy.ors = s.wx; gy.ops = (int64_t)Py * s.wx;
+        ColGeom gi{};
+        gi.ncols = s.M1; gi.n_in = Py; gi.n_out = Ny; gi.nouter = 1; gi.nplanes = B6 * Nz;
+        gi.irs = s.wx; gi.ips = (int64_t)Py * s.wx; gi.ors = s.wx; gi.ops = (int64_t)Ny * s.wx;
+        float ms = time_median(st, reps, [&] {
+            launch_col_fft<T>(Py, true, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gy, twp, tk, st);
+            launch_col_fft<T>(Py, false, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gi, twp, tk, st);
+        });
+        if (ms < best) { best = ms; out->tk_y = tk; out->ms[1] = ms; }
+    }
+    best = 1e30f;
+    for (int tk : tkz_list) {
+        ZGeom gz{};
+        gz.ncols = s.M1; gz.ntiles = (s.M1 + tk - 1) / tk; gz.nky = Py; gz.nz = Nz; gz.C = s.C; gz.B = s.B;
+        gz.irs = (int64_t)Py * s.wx; gz.iqs = (int64_t)Nz * Py * s.wx; gz.ios = s.wx;
+        gz.ors = gz.irs; gz.oqs = gz.iqs; gz.oos = gz.ios;
+        float ms = time_median(st, reps, [&] {
+            launch_z_fused<T>(Pz, w2.as<cplx<T>>(), w1.as<cplx<T>>(), spec.as<T>(), gz, twp, tk, st);
+        });
+        if (ms < best) { best = ms; out->tk_z = tk; out->ms[2] = ms; }
+    }
+    check_hip(hipStreamSynchronize(st), "tuning");
+}
+
 }  // namespace
 
 extern "C" {
@@ -375,7 +564,7 @@ ddstress_status ddstress_plan_footprint(const ddstress_desc* desc, size_t* cache
 }
 
 ddstress_status ddstress_plan_create(const ddstress_desc* desc, void* stream, ddstress_plan* out) {
-    return guarded([&] { create_plan(desc, static_cast<hipStream_t>(stream), out); });
+    return guarded([&] { create_plan(desc, nullptr, static_cast<hipStream_t>(stream), out); });
 }
 
 ddstress_status ddstress_set_density(ddstress_plan plan, const void* rho, int32_t where, void* stream) {
@@ -414,12 +603,33 @@ ddstress_status ddstress_stress(ddstress_plan plan, void* sigma, int32_t where, 
             dst = plan->sigma_tmp.p;
         }
         if (plan->shape.elem == 4)
-            run_stress<float>(plan, static_cast<const float*>(plan->rho), static_cast<float*>(dst), plan->shape.B, st);
+            enqueue_stress<float>(plan, static_cast<const float*>(plan->rho), static_cast<float*>(dst), plan->shape.B,
+                                  st);
         else
-            run_stress<double>(plan, static_cast<const double*>(plan->rho), static_cast<double*>(dst), plan->shape.B,
-                               st);
+            enqueue_stress<double>(plan, static_cast<const double*>(plan->rho), static_cast<double*>(dst),
+                                   plan->shape.B, st);
         if (where == DDSTRESS_HOST)
             check_hip(hipMemcpyAsync(sigma, dst, bytes, hipMemcpyDeviceToHost, st), "stress copy to host");
+    });
+}
+
+ddstress_status ddstress_autotune(const ddstress_desc* desc, void* stream, ddstress_tuning* out) {
+    return guarded([&] {
+        validate(desc);
+        if (!out) fail(DDSTRESS_E_INVALID, "output pointer is NULL");
+        std::memset(out, 0, sizeof(*out));
+        if (desc->precision == 32)
+            autotune_impl<float>(desc, static_cast<hipStream_t>(stream), out);
+        else
+            autotune_impl<double>(desc, static_cast<hipStream_t>(stream), out);
+    });
+}
+
+ddstress_status ddstress_plan_create_tuned(const ddstress_desc* desc, const ddstress_tuning* tuning, void* stream,
+                                           ddstress_plan* out) {
+    return guarded([&] {
+        if (!tuning) fail(DDSTRESS_E_INVALID, "tuning is NULL");
+        create_plan(desc, tuning, static_cast<hipStream_t>(stream), out);
     });
 }
 
@@ -433,6 +643,8 @@ ddstress_status ddstress_plan_share(ddstress_plan src, int32_t batch, ddstress_p
             p->desc = src->desc;
             p->desc.batch = batch;
             p->shape = make_shape(&p->desc);
+            p->shape.tkz = src->shape.tkz;      // the shared spectrum's tile layout
+            p->shape.ntz = src->shape.ntz;
             p->spec = src->spec;
             p->tw = src->tw;
             p->rows_x = src->rows_x;
@@ -458,9 +670,9 @@ ddstress_status ddstress_stress_batch(ddstress_plan plan, const void* rho, void*
         if (nbatch < 1 || nbatch > plan->shape.B) fail(DDSTRESS_E_INVALID, "nbatch must lie in [1, batch]");
         hipStream_t st = static_cast<hipStream_t>(stream);
         if (plan->shape.elem == 4)
-            run_stress<float>(plan, static_cast<const float*>(rho), static_cast<float*>(sigma), nbatch, st);
+            enqueue_stress<float>(plan, static_cast<const float*>(rho), static_cast<float*>(sigma), nbatch, st);
         else
-            run_stress<double>(plan, static_cast<const double*>(rho), static_cast<double*>(sigma), nbatch, st);
+            enqueue_stress<double>(plan, static_cast<const double*>(rho), static_cast<double*>(sigma), nbatch, st);
     });
 }
 
@@ -478,6 +690,8 @@ ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info) 
         info->batch = s.B;
         info->precision = plan->desc.precision;
         info->tile_z = s.tkz;
+        info->tile_y = plan->tk_y;
+        info->rows_x = plan->rows_x;
         info->cached_bytes = plan->spec->bytes + plan->tw->bytes;
         info->work_bytes = plan->work1.bytes + plan->work2.bytes + plan->rho_own.bytes + plan->sigma_tmp.bytes;
         info->kernel_real_max = plan->re_max;
@@ -492,6 +706,14 @@ ddstress_status ddstress_plan_set_profiling(ddstress_plan plan, int32_t enable) 
         plan->profiling = enable != 0;
         for (double& v : plan->pass_ms) v = 0.0;
         plan->timed_calls = 0;
+    });
+}
+
+ddstress_status ddstress_plan_set_graph(ddstress_plan plan, int32_t enable) {
+    return guarded([&] {
+        if (!plan) fail(DDSTRESS_E_INVALID, "plan is NULL");
+        plan->use_graph = enable != 0;
+        if (!plan->use_graph) plan->drop_graphs();
     });
 }
 

@@ -253,6 +253,7 @@ int default_z_tk(int N, int elem_bytes) {
     int tk = 256 / tc;
     if (tk < tk_min) tk = tk_min;
     while (tk > 1 && tk * tc > 512) tk /= 2;
+    while (tk > 1 && (int64_t)N * tk * 2 * elem_bytes > 64 * 1024) tk /= 2;
     return tk;
 }
 

@@ -1,0 +1,70 @@
+"""Autotuning cache: launch shapes chosen by ``ddstress_autotune`` per
+(device, grid, precision, channels, batch), kept in a JSON file.
+
+The cache file is ``$DDSTRESS_TUNE_CACHE`` or ``~/.cache/ddstress/tuning.json``.
+Tile choices do not change the arithmetic, so a tuned plan gives the same
+bits as a default one.
+"""
+import json
+import os
+import tempfile
+
+from . import binding as B
+
+
+def cache_path():
+    return os.environ.get("DDSTRESS_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ddstress", "tuning.json"))
+
+
+def shape_key(desc, device_name=""):
+    n = "x".join(str(v) for v in desc.n)
+    return f"{device_name}|{n}|fp{desc.precision}|C{3 * desc.n_lines}|B{desc.batch}"
+
+
+def _read(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _write(path, data):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=os.path.dirname(path), prefix=".tuning")
+    with os.fdopen(fd, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def to_dict(t):
+    return {"rows_x": t.rows_x, "tk_y": t.tk_y, "tk_z": t.tk_z, "ms": [round(float(v), 5) for v in t.ms]}
+
+
+def from_dict(d):
+    t = B.Tuning()
+    t.rows_x, t.tk_y, t.tk_z = int(d["rows_x"]), int(d["tk_y"]), int(d["tk_z"])
+    for i, v in enumerate(d.get("ms", [0, 0, 0])[:3]):
+        t.ms[i] = float(v)
+    return t
+
+
+def get_tuning(desc, stream=None, path=None, refresh=False):
+    """The cached tuning for this shape, running the autotuner on a miss."""
+    import torch
+    path = path or cache_path()
+    key = shape_key(desc, torch.cuda.get_device_name())
+    data = _read(path)
+    if not refresh and key in data:
+        return from_dict(data[key])
+    t = B.autotune(desc, stream)
+    data = _read(path)
+    data[key] = to_dict(t)
+    _write(path, data)
+    return t
+
+
+def tuned_plan(desc, stream=None, path=None):
+    """A plan built with the cached (or freshly measured) launch shapes."""
+    return B.Plan(desc, stream=stream, tuning=get_tuning(desc, stream, path))

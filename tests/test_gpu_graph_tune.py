@@ -1,0 +1,110 @@
+"""Graph replay and autotuned launch shapes (GPU).
+
+Graph replay and tile choices change how work is launched, not the
+arithmetic: every result is compared bit for bit with direct launches of a
+default plan. Graphs are replayed several times with eager work and
+synchronisations in between, and every replay is checked.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1804_01830_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_graph_replays_match_direct_launches(precision):
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w = W.random_field((24, 16, 8), n_lines=2, batch=2, seed=5, d=(1.0, 1.0, 2.0))
+    dt = torch.float32 if precision == 32 else torch.float64
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision, batch=2)
+    plan = B.Plan(desc)
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=dt).contiguous()
+    ref = torch.empty((2, 6, 8, 16, 24), dtype=dt, device="cuda")
+    plan.stress_batch(rho, ref, 2)
+    torch.cuda.synchronize()
+    plan.set_graph(True)
+    out = torch.empty_like(ref)
+    one = torch.empty((1, 6, 8, 16, 24), dtype=dt, device="cuda")
+    for rep in range(4):
+        out.fill_(float("nan"))
+        plan.stress_batch(rho, out, 2)              # captured on the first pass, replayed after
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {rep}"
+        junk = torch.randn(1 << 20, device="cuda", dtype=dt).sum()   # eager work between replays
+        one.zero_()
+        plan.stress_batch(rho, one, 1)               # a second graph for another batch size
+        torch.cuda.synchronize()
+        assert torch.equal(one[0], ref[0]) and torch.isfinite(junk)
+    plan.set_graph(False)
+    plan.close()
+
+
+def test_set_density_route_with_graphs():
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w = W.random_field((16, 16, 4), n_lines=1, seed=6)
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=32)
+    plan = B.Plan(desc)
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32)
+    plan.set_density(rho)
+    ref = plan.new_output()
+    plan.stress(ref)
+    plan.set_graph(True)
+    for _ in range(3):
+        out = plan.new_output()
+        plan.stress(out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+    plan.close()
+
+
+def test_autotuned_plan_is_bit_identical(tmp_path):
+    import torch
+    from paper_1804_01830_amd import binding as B
+    from paper_1804_01830_amd import tuning
+    w = W.random_field((40, 24, 12), n_lines=2, seed=8, d=(1.0, 1.0, 2.0))
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=32)
+    path = str(tmp_path / "tune.json")
+    t = tuning.get_tuning(desc, path=path)
+    assert t.rows_x >= 1 and t.tk_y >= 1 and t.tk_z >= 1 and all(v > 0 for v in t.ms)
+    data = json.load(open(path))
+    assert len(data) == 1 and list(data.values())[0]["tk_z"] == t.tk_z
+    again = tuning.get_tuning(desc, path=path)             # cache hit
+    assert (again.rows_x, again.tk_y, again.tk_z) == (t.rows_x, t.tk_y, t.tk_z)
+    tuned = tuning.tuned_plan(desc, path=path)
+    info = tuned.info()
+    assert (info.rows_x, info.tile_y, info.tile_z) == (t.rows_x, t.tk_y, t.tk_z)
+    plain = B.Plan(desc)
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32)
+    a = plain.new_output()
+    b = tuned.new_output()
+    plain.set_density(rho)
+    plain.stress(a)
+    tuned.set_density(rho)
+    tuned.stress(b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    shared = tuned.share(2)                                 # a shared plan keeps the tuned z tile
+    assert shared.info().tile_z == t.tk_z
+    c = torch.empty((1, 6, 12, 24, 40), dtype=torch.float32, device="cuda")
+    shared.stress_batch(rho, c, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(c, a)
+    for p in (shared, tuned, plain):
+        p.close()
+
+
+def test_tuning_outside_limits_is_rejected():
+    from paper_1804_01830_amd import binding as B
+    desc = B.make_desc((32, 32, 16), (1, 1, 1), 1.0, 0.3, [(0, 0, 1)], precision=32)
+    t = B.Tuning()
+    t.rows_x, t.tk_y, t.tk_z = 1, 4096, 16
+    with pytest.raises(B.DDStressError) as e:
+        B.Plan(desc, tuning=t)
+    assert e.value.status == B.E_INVALID
