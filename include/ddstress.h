@@ -97,18 +97,25 @@ typedef struct {
     int32_t tile_z;        /* columns per block of the fused z kernel (fixes the spectrum layout) */
     int32_t tile_y;        /* columns per block of the y passes */
     int32_t rows_x;        /* rows per block of the x passes */
+    int32_t ex, ey, ez;    /* element classes of the x, y and fused z passes (see ddstress_tuning) */
     size_t  cached_bytes;  /* device bytes held for the plan's lifetime (kernel spectrum, tables) */
     size_t  work_bytes;    /* device bytes of per-call work buffers */
     double  kernel_real_max;  /* max |Re K^| over the spectrum: zero up to rounding (K is odd) */
     double  kernel_imag_max;  /* max |Im K^| */
 } ddstress_info;
 
-/* Launch shapes of the passes: a tuning choice. Tile choices change which
- * threads do the work, not the arithmetic: results are bit-identical. */
+/* Launch shapes of the passes: a tuning choice. A transform of length N runs
+ * with E = min(N, e) elements per thread and radices <= E, where the element
+ * class e is 8 or 16 for the x and y passes and 4 or 8 (FP32) / 2 or 4 (FP64)
+ * for the fused z pass; 0 selects the default. Tile sizes change which
+ * threads do the work, not the arithmetic (bit-identical results); element
+ * classes change the radix sequence and hence the rounding (within the
+ * stated tolerances). */
 typedef struct {
     int32_t rows_x;        /* rows per block of the x passes (forward and inverse) */
     int32_t tk_y;          /* consecutive kx columns per block of the y passes */
     int32_t tk_z;          /* consecutive kx columns per block of the fused z pass */
+    int32_t ex, ey, ez;    /* element classes of the x, y and fused z passes (0: default) */
     float   ms[3];         /* autotune: median device ms of the chosen x pair, y pair and z pass */
 } ddstress_tuning;
 
@@ -128,8 +135,8 @@ ddstress_status ddstress_plan_footprint(const ddstress_desc* desc, size_t* cache
  * device memory until ddstress_plan_destroy. */
 ddstress_status ddstress_plan_create(const ddstress_desc* desc, void* stream, ddstress_plan* out);
 
-/* Autotuner: times every admissible tile choice of each pass (threads per
- * block <= 512, LDS <= 64 KiB) on zero-filled buffers of the descriptor's
+/* Autotuner: times every admissible tile size and element class of each pass
+ * (threads per block <= 512, LDS <= 64 KiB) on zero-filled buffers of the descriptor's
  * shape, precision and batch, with HIP events on `stream` (median of five runs
  * after two warm-up runs), and returns the fastest per pass. Synchronous;
  * allocates its buffers for the duration of the call. */

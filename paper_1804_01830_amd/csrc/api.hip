@@ -1,6 +1,8 @@
 // C entry points: plan construction, density hand-over and the stress call.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -162,7 +164,8 @@ struct ddstress_plan_s {
     DevBuf sigma_tmp;   // stress staging for HOST output
     const void* rho = nullptr;
     bool have_density = false;
-    int rows_x = 1, tk_y = 1;
+    int rows_x = 1, tk_y = 1;      // x rows and y columns per block
+    int ex = 16, ey = 16, ez = 8;  // element classes of the x, y and fused z passes
     double re_max = 0.0, im_max = 0.0;
     // per-pass event timing: events are pooled and reused between folds
     bool profiling = false;
@@ -239,7 +242,8 @@ void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
         KernelParams kp = make_kernel_params(p->desc, l, s.P);
         launch_kernel_build(kp, kr.as<double>(), st);
         // x: 18 * Pz * Py rows of Px reals (no padding: the coefficients fill the grid)
-        launch_x_r2c<double>(s.M, kr.as<double>(), kc.as<cplx<double>>(), 18LL * s.P[2] * s.P[1], s.P[0],
+        launch_x_r2c<double>(s.M, default_ev_col(s.M), kr.as<double>(), kc.as<cplx<double>>(),
+                             18LL * s.P[2] * s.P[1], s.P[0],
                              s.P[0], s.wx, tw, rows, st);
         ColGeom gy{};
         gy.ncols = s.M1;
@@ -250,7 +254,8 @@ void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
         gy.irs = gy.ors = s.wx;
         gy.ios = gy.oos = 0;
         gy.ips = gy.ops = (int64_t)s.P[1] * s.wx;
-        launch_col_fft<double>(s.P[1], true, kc.as<cplx<double>>(), kc.as<cplx<double>>(), gy, tw, tky, st);
+        launch_col_fft<double>(s.P[1], default_ev_col(s.P[1]), true, kc.as<cplx<double>>(), kc.as<cplx<double>>(),
+                               gy, tw, tky, st);
         ColGeom gz{};
         gz.ncols = s.M1;
         gz.n_in = s.P[2];
@@ -260,7 +265,8 @@ void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
         gz.irs = gz.ors = (int64_t)s.P[1] * s.wx;
         gz.ios = gz.oos = s.wx;
         gz.ips = gz.ops = plane_c;
-        launch_col_fft<double>(s.P[2], true, kc.as<cplx<double>>(), kc.as<cplx<double>>(), gz, tw, tkz, st);
+        launch_col_fft<double>(s.P[2], default_ev_col(s.P[2]), true, kc.as<cplx<double>>(), kc.as<cplx<double>>(),
+                               gz, tw, tkz, st);
         launch_extract<T>(kc.as<cplx<double>>(), p->spec->as<T>(), l, s.C, s.M1, s.wx, s.P[1], s.P[2], s.tkz,
                           s.ntz, inv_p, maxbits.as<unsigned long long>(), st);
     }
@@ -295,7 +301,7 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2], Py = s.P[1];
     p->mark(st);
     // x forward: rows (b, c, z, y) of Nx reals -> M+1 complex
-    launch_x_r2c<T>(s.M, rho, w1, BC * Nz * Ny, Nx, Nx, s.wx, tw, p->rows_x, st);
+    launch_x_r2c<T>(s.M, p->ex, rho, w1, BC * Nz * Ny, Nx, Nx, s.wx, tw, p->rows_x, st);
     p->mark(st);
     // y forward: Ny rows -> Py rows
     ColGeom gy{};
@@ -308,7 +314,7 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     gy.ips = (int64_t)Ny * s.wx;
     gy.ors = s.wx;
     gy.ops = (int64_t)Py * s.wx;
-    launch_col_fft<T>(Py, true, w1, w2, gy, tw, p->tk_y, st);
+    launch_col_fft<T>(Py, p->ey, true, w1, w2, gy, tw, p->tk_y, st);
     p->mark(st);
     // z forward + contraction + z inverse
     ZGeom gz{};
@@ -324,7 +330,7 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     gz.ors = gz.irs;
     gz.oqs = gz.iqs;
     gz.oos = gz.ios;
-    launch_z_fused<T>(s.P[2], w2, w1, p->spec->as<T>(), gz, tw, s.tkz, st);
+    launch_z_fused<T>(s.P[2], p->ez, w2, w1, p->spec->as<T>(), gz, tw, s.tkz, st);
     p->mark(st);
     // y inverse: Py rows -> Ny rows
     ColGeom gi{};
@@ -337,10 +343,10 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     gi.ips = (int64_t)Py * s.wx;
     gi.ors = s.wx;
     gi.ops = (int64_t)Ny * s.wx;
-    launch_col_fft<T>(Py, false, w1, w2, gi, tw, p->tk_y, st);
+    launch_col_fft<T>(Py, p->ey, false, w1, w2, gi, tw, p->tk_y, st);
     p->mark(st);
     // x inverse: rows (b, v, z, y) -> Nx reals
-    launch_x_c2r<T>(s.M, w2, sigma, B6 * Nz * Ny, Nx, s.wx, Nx, tw, p->rows_x, st);
+    launch_x_c2r<T>(s.M, p->ex, w2, sigma, B6 * Nz * Ny, Nx, s.wx, Nx, tw, p->rows_x, st);
     p->mark(st);
 }
 
@@ -392,26 +398,39 @@ void enqueue_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStrea
 // Launch-shape limits shared by the defaults, the autotuner and tuned plans.
 constexpr int kMaxThreads = 512;
 constexpr size_t kMaxLds = 64 * 1024;
-bool rows_ok(const Shape& s, int r) {
-    return r >= 1 && r * (s.M / elems_for(s.M)) <= kMaxThreads && (size_t)r * (s.M + 1) * 2 * s.elem <= kMaxLds;
+bool rows_ok(const Shape& s, int r, int ev) {
+    return r >= 1 && ev_col_ok(ev) && x_threads(s.M, r, ev) <= kMaxThreads &&
+           (size_t)r * (s.M + 1) * 2 * s.elem <= kMaxLds;
 }
-bool col_ok(const Shape& s, int N, int tk) {
-    return tk >= 1 && col_threads(N, tk) <= kMaxThreads && (size_t)N * tk * 2 * s.elem <= kMaxLds;
+bool col_ok(const Shape& s, int N, int tk, int ev) {
+    return tk >= 1 && ev_col_ok(ev) && col_threads(N, tk, ev) <= kMaxThreads &&
+           (size_t)N * tk * 2 * s.elem <= kMaxLds;
 }
-bool z_ok(const Shape& s, int tk) {
-    return tk >= 1 && z_threads(s.P[2], tk, s.elem) <= kMaxThreads && (size_t)s.P[2] * tk * 2 * s.elem <= kMaxLds;
+bool z_ok(const Shape& s, int tk, int ev) {
+    return tk >= 1 && ev_z_ok(ev, s.elem) && z_threads(s.P[2], tk, ev) <= kMaxThreads &&
+           (size_t)s.P[2] * tk * 2 * s.elem <= kMaxLds;
 }
 
-void apply_tuning(Shape& s, int& rows_x, int& tk_y, const ddstress_tuning* t) {
-    rows_x = default_rows(s.M, s.elem);
-    tk_y = default_col_tk(s.P[1], s.elem);
-    if (!t) return;
-    if (!rows_ok(s, t->rows_x) || !col_ok(s, s.P[1], t->tk_y) || !z_ok(s, t->tk_z))
+struct LaunchChoice {
+    int rows_x, ex, tk_y, ey, ez;
+};
+
+LaunchChoice default_launch(const Shape& s) {
+    return {default_rows(s.M, s.elem), default_ev_col(s.M), default_col_tk(s.P[1], s.elem), default_ev_col(s.P[1]),
+            default_ev_z(s.elem)};
+}
+
+// Apply a tuning (zero element classes select the defaults) after checking it.
+LaunchChoice apply_tuning(Shape& s, const ddstress_tuning* t) {
+    LaunchChoice c = default_launch(s);
+    if (!t) return c;
+    const int ex = t->ex ? t->ex : c.ex, ey = t->ey ? t->ey : c.ey, ez = t->ez ? t->ez : c.ez;
+    if (!rows_ok(s, t->rows_x, ex) || !col_ok(s, s.P[1], t->tk_y, ey) || !z_ok(s, t->tk_z, ez))
         fail(DDSTRESS_E_INVALID, "tuning choice outside the launch limits of this shape");
-    rows_x = t->rows_x;
-    tk_y = t->tk_y;
+    c = {t->rows_x, ex, t->tk_y, ey, ez};
     s.tkz = t->tk_z;
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
+    return c;
 }
 
 void create_plan(const ddstress_desc* desc, const ddstress_tuning* tuning, hipStream_t st, ddstress_plan* out) {
@@ -422,7 +441,12 @@ void create_plan(const ddstress_desc* desc, const ddstress_tuning* tuning, hipSt
     try {
         p->desc = *desc;
         p->shape = make_shape(desc);
-        apply_tuning(p->shape, p->rows_x, p->tk_y, tuning);
+        const LaunchChoice lc = apply_tuning(p->shape, tuning);
+        p->rows_x = lc.rows_x;
+        p->ex = lc.ex;
+        p->tk_y = lc.tk_y;
+        p->ey = lc.ey;
+        p->ez = lc.ez;
         const Shape& s = p->shape;
         p->spec = std::make_shared<DevBuf>();
         p->tw = std::make_shared<DevBuf>();
@@ -480,15 +504,17 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
     Shape s = make_shape(desc);
     const int64_t BC = (int64_t)s.B * s.C, B6 = (int64_t)s.B * 6;
     const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2], Py = s.P[1], Pz = s.P[2];
-    std::vector<int> tkz_list;
-    for (int tk = 1; tk <= 256; tk *= 2)
-        if (z_ok(s, tk) && z_threads(Pz, tk, s.elem) >= 64) tkz_list.push_back(tk);
-    if (tkz_list.empty()) tkz_list.push_back(s.tkz);
+    const std::vector<int> zev = s.elem == 4 ? std::vector<int>{4, 8} : std::vector<int>{2, 4};
+    std::vector<std::pair<int, int>> zlist;     // (tk, ev)
+    for (int ev : zev)
+        for (int tk = 1; tk <= 256; tk *= 2)
+            if (z_ok(s, tk, ev) && z_threads(Pz, tk, ev) >= 64) zlist.push_back({tk, ev});
+    if (zlist.empty()) zlist.push_back({s.tkz, default_ev_z(s.elem)});
     size_t spec_max = 0;
-    for (int tk : tkz_list) {
+    for (auto& z : zlist) {
         Shape t = s;
-        t.tkz = tk;
-        t.ntz = (s.M1 + tk - 1) / tk;
+        t.tkz = z.first;
+        t.ntz = (s.M1 + z.first - 1) / z.first;
         spec_max = std::max(spec_max, spec_bytes(t));
     }
     DevBuf rho, sig, w1, w2, spec, tw;
@@ -508,41 +534,48 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
     check_hip(hipStreamSynchronize(st), "tuning setup");
     const cplx<T>* twp = tw.as<cplx<T>>();
     const int reps = 5;
+    const bool verbose = std::getenv("DDSTRESS_TUNE_VERBOSE") != nullptr;
 
     float best = 1e30f;
-    for (int r = 1; r <= kMaxThreads; r *= 2) {
-        if (!rows_ok(s, r)) continue;
-        float ms = time_median(st, reps, [&] {
-            launch_x_r2c<T>(s.M, rho.as<T>(), w1.as<cplx<T>>(), BC * Nz * Ny, Nx, Nx, s.wx, twp, r, st);
-            launch_x_c2r<T>(s.M, w2.as<cplx<T>>(), sig.as<T>(), B6 * Nz * Ny, Nx, s.wx, Nx, twp, r, st);
-        });
-        if (ms < best) { best = ms; out->rows_x = r; out->ms[0] = ms; }
-    }
+    for (int ev : {8, 16})
+        for (int r = 1; r <= kMaxThreads; r *= 2) {
+            if (!rows_ok(s, r, ev) || (ev == 16 && s.M <= 8)) continue;
+            float ms = time_median(st, reps, [&] {
+                launch_x_r2c<T>(s.M, ev, rho.as<T>(), w1.as<cplx<T>>(), BC * Nz * Ny, Nx, Nx, s.wx, twp, r, st);
+                launch_x_c2r<T>(s.M, ev, w2.as<cplx<T>>(), sig.as<T>(), B6 * Nz * Ny, Nx, s.wx, Nx, twp, r, st);
+            });
+            if (verbose) std::fprintf(stderr, "[tune] x rows=%d ev=%d %.5f ms\n", r, ev, ms);
+            if (ms < best) { best = ms; out->rows_x = r; out->ex = ev; out->ms[0] = ms; }
+        }
     best = 1e30f;
-    for (int tk = 1; tk <= 256; tk *= 2) {
-        if (!col_ok(s, Py, tk) || col_threads(Py, tk) < 64) continue;
-        ColGeom gy{};
-        gy.ncols = s.M1; gy.n_in = Ny; gy.n_out = Py; gy.nouter = 1; gy.nplanes = BC * Nz;
-        gy.irs = s.wx; gy.ips = (int64_t)Ny * s.wx; gy.ors = s.wx; gy.ops = (int64_t)Py * s.wx;
-        ColGeom gi{};
-        gi.ncols = s.M1; gi.n_in = Py; gi.n_out = Ny; gi.nouter = 1; gi.nplanes = B6 * Nz;
-        gi.irs = s.wx; gi.ips = (int64_t)Py * s.wx; gi.ors = s.wx; gi.ops = (int64_t)Ny * s.wx;
-        float ms = time_median(st, reps, [&] {
-            launch_col_fft<T>(Py, true, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gy, twp, tk, st);
-            launch_col_fft<T>(Py, false, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gi, twp, tk, st);
-        });
-        if (ms < best) { best = ms; out->tk_y = tk; out->ms[1] = ms; }
-    }
+    for (int ev : {8, 16})
+        for (int tk = 1; tk <= 256; tk *= 2) {
+            if (!col_ok(s, Py, tk, ev) || col_threads(Py, tk, ev) < 64 || (ev == 16 && Py <= 8)) continue;
+            ColGeom gy{};
+            gy.ncols = s.M1; gy.n_in = Ny; gy.n_out = Py; gy.nouter = 1; gy.nplanes = BC * Nz;
+            gy.irs = s.wx; gy.ips = (int64_t)Ny * s.wx; gy.ors = s.wx; gy.ops = (int64_t)Py * s.wx;
+            ColGeom gi{};
+            gi.ncols = s.M1; gi.n_in = Py; gi.n_out = Ny; gi.nouter = 1; gi.nplanes = B6 * Nz;
+            gi.irs = s.wx; gi.ips = (int64_t)Py * s.wx; gi.ors = s.wx; gi.ops = (int64_t)Ny * s.wx;
+            float ms = time_median(st, reps, [&] {
+                launch_col_fft<T>(Py, ev, true, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gy, twp, tk, st);
+                launch_col_fft<T>(Py, ev, false, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gi, twp, tk, st);
+            });
+            if (verbose) std::fprintf(stderr, "[tune] y tk=%d ev=%d %.5f ms\n", tk, ev, ms);
+            if (ms < best) { best = ms; out->tk_y = tk; out->ey = ev; out->ms[1] = ms; }
+        }
     best = 1e30f;
-    for (int tk : tkz_list) {
+    for (auto& z : zlist) {
+        const int tk = z.first, ev = z.second;
         ZGeom gz{};
         gz.ncols = s.M1; gz.ntiles = (s.M1 + tk - 1) / tk; gz.nky = Py; gz.nz = Nz; gz.C = s.C; gz.B = s.B;
         gz.irs = (int64_t)Py * s.wx; gz.iqs = (int64_t)Nz * Py * s.wx; gz.ios = s.wx;
         gz.ors = gz.irs; gz.oqs = gz.iqs; gz.oos = gz.ios;
         float ms = time_median(st, reps, [&] {
-            launch_z_fused<T>(Pz, w2.as<cplx<T>>(), w1.as<cplx<T>>(), spec.as<T>(), gz, twp, tk, st);
+            launch_z_fused<T>(Pz, ev, w2.as<cplx<T>>(), w1.as<cplx<T>>(), spec.as<T>(), gz, twp, tk, st);
         });
-        if (ms < best) { best = ms; out->tk_z = tk; out->ms[2] = ms; }
+        if (verbose) std::fprintf(stderr, "[tune] z tk=%d ev=%d %.5f ms\n", tk, ev, ms);
+        if (ms < best) { best = ms; out->tk_z = tk; out->ez = ev; out->ms[2] = ms; }
     }
     check_hip(hipStreamSynchronize(st), "tuning");
 }
@@ -649,6 +682,9 @@ ddstress_status ddstress_plan_share(ddstress_plan src, int32_t batch, ddstress_p
             p->tw = src->tw;
             p->rows_x = src->rows_x;
             p->tk_y = src->tk_y;
+            p->ex = src->ex;
+            p->ey = src->ey;
+            p->ez = src->ez;
             p->re_max = src->re_max;
             p->im_max = src->im_max;
             const Shape& s = p->shape;
@@ -692,6 +728,9 @@ ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info) 
         info->tile_z = s.tkz;
         info->tile_y = plan->tk_y;
         info->rows_x = plan->rows_x;
+        info->ex = plan->ex;
+        info->ey = plan->ey;
+        info->ez = plan->ez;
         info->cached_bytes = plan->spec->bytes + plan->tw->bytes;
         info->work_bytes = plan->work1.bytes + plan->work2.bytes + plan->rho_own.bytes + plan->sigma_tmp.bytes;
         info->kernel_real_max = plan->re_max;

@@ -40,22 +40,14 @@ constexpr int kTwiddleEntries = 2 * kMaxLen;
 template <typename T>
 void fill_twiddles(cplx<T>* host);   // kTwiddleEntries entries
 
-// Launch geometry of one pass.
-struct ColLaunch {
-    int tk;        // columns per block
-};
-struct RowLaunch {
-    int rows;      // rows per block
-};
-
 // ---- pass launchers (passes.hip) -------------------------------------------
 // Real-to-complex transform of length P = 2M along contiguous rows.
 template <typename T>
-void launch_x_r2c(int M, const T* in, cplx<T>* out, int64_t nrows, int n_in, int64_t in_stride,
+void launch_x_r2c(int M, int ev, const T* in, cplx<T>* out, int64_t nrows, int n_in, int64_t in_stride,
                   int64_t out_stride, const cplx<T>* tw, int rows_per_block, hipStream_t s);
 // Complex-to-real transform of length P = 2M along rows, keeping n_out reals.
 template <typename T>
-void launch_x_c2r(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
+void launch_x_c2r(int M, int ev, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
                   int64_t out_stride, const cplx<T>* tw, int rows_per_block, hipStream_t s);
 // Complex transform of length N along a strided axis, on tiles of consecutive columns.
 struct ColGeom {
@@ -66,7 +58,7 @@ struct ColGeom {
     int64_t ors, oos, ops; // output strides
 };
 template <typename T>
-void launch_col_fft(int N, bool forward, const cplx<T>* in, cplx<T>* out, const ColGeom& g,
+void launch_col_fft(int N, int ev, bool forward, const cplx<T>* in, cplx<T>* out, const ColGeom& g,
                     const cplx<T>* tw, int tk, hipStream_t s);
 // Fused forward z transform, contraction with the kernel spectrum and inverse z.
 struct ZGeom {
@@ -79,15 +71,20 @@ struct ZGeom {
     int64_t ors, oqs, oos; // output strides (6B planes)
 };
 template <typename T>
-void launch_z_fused(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+void launch_z_fused(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
                     const cplx<T>* tw, int tk, hipStream_t s);
 
-// Default launch geometry.
+// Launch geometry: threads per block, element classes and defaults.
+int x_threads(int M, int rows, int ev);
+int col_threads(int N, int tk, int ev);
+int z_threads(int N, int tk, int ev);
+int default_ev_col(int N);
+int default_ev_z(int elem_bytes);
+bool ev_col_ok(int ev);
+bool ev_z_ok(int ev, int elem_bytes);
 int default_col_tk(int N, int elem_bytes);
 int default_rows(int M, int elem_bytes);
 int default_z_tk(int N, int elem_bytes);
-int col_threads(int N, int tk);
-int z_threads(int N, int tk, int elem_bytes);
 
 // ---- kernel build (kernel_build.hip) ---------------------------------------
 struct KernelParams {

@@ -224,13 +224,22 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
 }
 
 // ----------------------------------------------------------------------------
-// Launch geometry and dispatch over the power-of-two lengths.
+// Launch geometry and dispatch. A transform of length N runs with
+// E = min(N, ev) elements per thread, where the element class ev is a tuning
+// choice (it also bounds the radix, R <= E): 8 or 16 for the x and y passes;
+// 4 or 8 (FP32), 2 or 4 (FP64) for the fused z pass.
 // ----------------------------------------------------------------------------
-int col_threads(int N, int tk) { return tk * (N / elems_for(N)); }
-int z_threads(int N, int tk, int elem_bytes) { return tk * (N / elems_fused(N, elem_bytes)); }
+static int ecount(int N, int ev) { return N < ev ? N : ev; }
+int x_threads(int M, int rows, int ev) { return rows * (M / ecount(M, ev)); }
+int col_threads(int N, int tk, int ev) { return tk * (N / ecount(N, ev)); }
+int z_threads(int N, int tk, int ev) { return tk * (N / ecount(N, ev)); }
+int default_ev_col(int N) { return N <= 64 ? 8 : 16; }
+int default_ev_z(int elem_bytes) { return elem_bytes <= 4 ? 8 : 4; }
+bool ev_col_ok(int ev) { return ev == 8 || ev == 16; }
+bool ev_z_ok(int ev, int elem_bytes) { return elem_bytes <= 4 ? (ev == 4 || ev == 8) : (ev == 2 || ev == 4); }
 
 int default_col_tk(int N, int elem_bytes) {
-    const int tc = N / elems_for(N);
+    const int tc = N / ecount(N, default_ev_col(N));
     const int tk_min = elem_bytes <= 4 ? 16 : 8;
     int tk = 256 / tc;
     if (tk < tk_min) tk = tk_min;
@@ -240,7 +249,7 @@ int default_col_tk(int N, int elem_bytes) {
 }
 
 int default_rows(int M, int elem_bytes) {
-    const int tc = M / elems_for(M);
+    const int tc = M / ecount(M, default_ev_col(M));
     int rows = 256 / tc;
     if (rows < 1) rows = 1;
     while (rows > 1 && (int64_t)rows * (M + 1) * 2 * elem_bytes > 64 * 1024) rows /= 2;
@@ -248,7 +257,7 @@ int default_rows(int M, int elem_bytes) {
 }
 
 int default_z_tk(int N, int elem_bytes) {
-    const int tc = N / elems_fused(N, elem_bytes);
+    const int tc = N / ecount(N, default_ev_z(elem_bytes));
     const int tk_min = elem_bytes <= 4 ? 16 : 8;
     int tk = 256 / tc;
     if (tk < tk_min) tk = tk_min;
@@ -257,107 +266,143 @@ int default_z_tk(int N, int elem_bytes) {
     return tk;
 }
 
-#define DDS_FOR_LENGTHS(X) X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
+#define DDS_FOR_LENGTHS(X, EV) X(1, EV) X(2, EV) X(4, EV) X(8, EV) X(16, EV) X(32, EV) X(64, EV) \
+    X(128, EV) X(256, EV) X(512, EV) X(1024, EV)
 
-template <typename T>
-void launch_x_r2c(int M, const T* in, cplx<T>* out, int64_t nrows, int n_in, int64_t in_stride,
-                  int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
-    if (nrows <= 0) return;
+template <typename T, int EV>
+static void x_r2c_ev(int M, const T* in, cplx<T>* out, int64_t nrows, int n_in, int64_t in_stride,
+                     int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
     const int64_t blocks = (nrows + rows - 1) / rows;
     const size_t lds = (size_t)rows * (M + 1) * sizeof(cplx<T>);
     switch (M) {
-#define X_CASE(L)                                                                              \
-    case L: {                                                                                  \
-        constexpr int E = elems_for(L);                                                        \
-        hipLaunchKernelGGL((k_x_r2c<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, \
-                           in, out, nrows, n_in, in_stride, out_stride, tw, rows);             \
-        break;                                                                                 \
+#define X_CASE(L, EVV)                                                                                     \
+    case L: {                                                                                              \
+        constexpr int E = L < EVV ? L : EVV;                                                               \
+        hipLaunchKernelGGL((k_x_r2c<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, in, out, \
+                           nrows, n_in, in_stride, out_stride, tw, rows);                                  \
+        break;                                                                                             \
     }
-        DDS_FOR_LENGTHS(X_CASE)
+        DDS_FOR_LENGTHS(X_CASE, EV)
 #undef X_CASE
         default: fail(DDSTRESS_E_UNSUPPORTED, "x transform length not supported");
     }
+}
+
+template <typename T, int EV>
+static void x_c2r_ev(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
+                     int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
+    const int64_t blocks = (nrows + rows - 1) / rows;
+    const size_t lds = (size_t)rows * (M + 1) * sizeof(cplx<T>);
+    switch (M) {
+#define X_CASE(L, EVV)                                                                                     \
+    case L: {                                                                                              \
+        constexpr int E = L < EVV ? L : EVV;                                                               \
+        hipLaunchKernelGGL((k_x_c2r<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, in, out, \
+                           nrows, n_out, in_stride, out_stride, tw, rows);                                 \
+        break;                                                                                             \
+    }
+        DDS_FOR_LENGTHS(X_CASE, EV)
+#undef X_CASE
+        default: fail(DDSTRESS_E_UNSUPPORTED, "x transform length not supported");
+    }
+}
+
+template <typename T, int EV, bool FWD>
+static void col_ev(int N, const cplx<T>* in, cplx<T>* out, const ColGeom& g, const cplx<T>* tw, int tk,
+                   int64_t ntiles, int64_t blocks, hipStream_t s) {
+    const size_t lds = (size_t)N * tk * sizeof(cplx<T>);
+    switch (N) {
+#define C_CASE(L, EVV)                                                                                     \
+    case L: {                                                                                              \
+        constexpr int E = L < EVV ? L : EVV;                                                               \
+        hipLaunchKernelGGL((k_col_fft<T, L, E, FWD>), dim3((unsigned)blocks), dim3(tk * (L / E)), lds, s, in, \
+                           out, g, tw, tk, ntiles);                                                        \
+        break;                                                                                             \
+    }
+        DDS_FOR_LENGTHS(C_CASE, EV)
+#undef C_CASE
+        default: fail(DDSTRESS_E_UNSUPPORTED, "column transform length not supported");
+    }
+}
+
+template <typename T, int EV>
+static void z_ev(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g, const cplx<T>* tw,
+                 int tk, int64_t blocks, hipStream_t s) {
+    const size_t lds = (size_t)N * tk * sizeof(cplx<T>);
+    switch (N) {
+#define Z_CASE(L, EVV)                                                                                     \
+    case L: {                                                                                              \
+        constexpr int E = L < EVV ? L : EVV;                                                               \
+        hipLaunchKernelGGL((k_z_fused<T, L, E>), dim3((unsigned)blocks), dim3(tk * (L / E)), lds, s, in, out, \
+                           spec, g, tw, tk);                                                               \
+        break;                                                                                             \
+    }
+        DDS_FOR_LENGTHS(Z_CASE, EV)
+#undef Z_CASE
+        default: fail(DDSTRESS_E_UNSUPPORTED, "z transform length not supported");
+    }
+}
+
+template <typename T>
+void launch_x_r2c(int M, int ev, const T* in, cplx<T>* out, int64_t nrows, int n_in, int64_t in_stride,
+                  int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
+    if (nrows <= 0) return;
+    if (ev == 8) x_r2c_ev<T, 8>(M, in, out, nrows, n_in, in_stride, out_stride, tw, rows, s);
+    else if (ev == 16) x_r2c_ev<T, 16>(M, in, out, nrows, n_in, in_stride, out_stride, tw, rows, s);
+    else fail(DDSTRESS_E_INVALID, "x element class must be 8 or 16");
     check_hip(hipGetLastError(), "x r2c launch");
 }
 
 template <typename T>
-void launch_x_c2r(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
+void launch_x_c2r(int M, int ev, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
                   int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
     if (nrows <= 0) return;
-    const int64_t blocks = (nrows + rows - 1) / rows;
-    const size_t lds = (size_t)rows * (M + 1) * sizeof(cplx<T>);
-    switch (M) {
-#define X_CASE(L)                                                                              \
-    case L: {                                                                                  \
-        constexpr int E = elems_for(L);                                                        \
-        hipLaunchKernelGGL((k_x_c2r<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, \
-                           in, out, nrows, n_out, in_stride, out_stride, tw, rows);            \
-        break;                                                                                 \
-    }
-        DDS_FOR_LENGTHS(X_CASE)
-#undef X_CASE
-        default: fail(DDSTRESS_E_UNSUPPORTED, "x transform length not supported");
-    }
+    if (ev == 8) x_c2r_ev<T, 8>(M, in, out, nrows, n_out, in_stride, out_stride, tw, rows, s);
+    else if (ev == 16) x_c2r_ev<T, 16>(M, in, out, nrows, n_out, in_stride, out_stride, tw, rows, s);
+    else fail(DDSTRESS_E_INVALID, "x element class must be 8 or 16");
     check_hip(hipGetLastError(), "x c2r launch");
 }
 
 template <typename T>
-void launch_col_fft(int N, bool forward, const cplx<T>* in, cplx<T>* out, const ColGeom& g,
+void launch_col_fft(int N, int ev, bool forward, const cplx<T>* in, cplx<T>* out, const ColGeom& g,
                     const cplx<T>* tw, int tk, hipStream_t s) {
     const int64_t ntiles = (g.ncols + tk - 1) / tk;
     const int64_t blocks = ntiles * g.nouter * g.nplanes;
     if (blocks <= 0) return;
     if (blocks > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
-    const size_t lds = (size_t)N * tk * sizeof(cplx<T>);
-    switch (N) {
-#define C_CASE(L)                                                                              \
-    case L: {                                                                                  \
-        constexpr int E = elems_for(L);                                                        \
-        if (forward)                                                                           \
-            hipLaunchKernelGGL((k_col_fft<T, L, E, true>), dim3((unsigned)blocks), dim3(tk * (L / E)), \
-                               lds, s, in, out, g, tw, tk, ntiles);                            \
-        else                                                                                   \
-            hipLaunchKernelGGL((k_col_fft<T, L, E, false>), dim3((unsigned)blocks), dim3(tk * (L / E)), \
-                               lds, s, in, out, g, tw, tk, ntiles);                            \
-        break;                                                                                 \
-    }
-        DDS_FOR_LENGTHS(C_CASE)
-#undef C_CASE
-        default: fail(DDSTRESS_E_UNSUPPORTED, "column transform length not supported");
-    }
+    if (ev == 8 && forward) col_ev<T, 8, true>(N, in, out, g, tw, tk, ntiles, blocks, s);
+    else if (ev == 8) col_ev<T, 8, false>(N, in, out, g, tw, tk, ntiles, blocks, s);
+    else if (ev == 16 && forward) col_ev<T, 16, true>(N, in, out, g, tw, tk, ntiles, blocks, s);
+    else if (ev == 16) col_ev<T, 16, false>(N, in, out, g, tw, tk, ntiles, blocks, s);
+    else fail(DDSTRESS_E_INVALID, "column element class must be 8 or 16");
     check_hip(hipGetLastError(), "column fft launch");
 }
 
 template <typename T>
-void launch_z_fused(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+void launch_z_fused(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
                     const cplx<T>* tw, int tk, hipStream_t s) {
     const int64_t blocks = (int64_t)g.ntiles * g.nky;
     if (blocks <= 0) return;
-    const size_t lds = (size_t)N * tk * sizeof(cplx<T>);
-    switch (N) {
-#define Z_CASE(L)                                                                              \
-    case L: {                                                                                  \
-        constexpr int E = elems_fused(L, (int)sizeof(T));                                      \
-        hipLaunchKernelGGL((k_z_fused<T, L, E>), dim3((unsigned)blocks), dim3(tk * (L / E)), lds, s, \
-                           in, out, spec, g, tw, tk);                                          \
-        break;                                                                                 \
-    }
-        DDS_FOR_LENGTHS(Z_CASE)
-#undef Z_CASE
-        default: fail(DDSTRESS_E_UNSUPPORTED, "z transform length not supported");
+    if (!ev_z_ok(ev, (int)sizeof(T))) fail(DDSTRESS_E_INVALID, "z element class not supported for this precision");
+    if constexpr (sizeof(T) == 4) {
+        if (ev == 4) z_ev<T, 4>(N, in, out, spec, g, tw, tk, blocks, s);
+        else z_ev<T, 8>(N, in, out, spec, g, tw, tk, blocks, s);
+    } else {
+        if (ev == 2) z_ev<T, 2>(N, in, out, spec, g, tw, tk, blocks, s);
+        else z_ev<T, 4>(N, in, out, spec, g, tw, tk, blocks, s);
     }
     check_hip(hipGetLastError(), "fused z launch");
 }
 
-#define INSTANTIATE(T)                                                                         \
-    template void launch_x_r2c<T>(int, const T*, cplx<T>*, int64_t, int, int64_t, int64_t,       \
-                                  const cplx<T>*, int, hipStream_t);                           \
-    template void launch_x_c2r<T>(int, const cplx<T>*, T*, int64_t, int, int64_t, int64_t,       \
-                                  const cplx<T>*, int, hipStream_t);                           \
-    template void launch_col_fft<T>(int, bool, const cplx<T>*, cplx<T>*, const ColGeom&,         \
-                                    const cplx<T>*, int, hipStream_t);                         \
-    template void launch_z_fused<T>(int, const cplx<T>*, cplx<T>*, const T*, const ZGeom&,       \
-                                    const cplx<T>*, int, hipStream_t);
+#define INSTANTIATE(T)                                                                                     \
+    template void launch_x_r2c<T>(int, int, const T*, cplx<T>*, int64_t, int, int64_t, int64_t, const cplx<T>*, \
+                                  int, hipStream_t);                                                       \
+    template void launch_x_c2r<T>(int, int, const cplx<T>*, T*, int64_t, int, int64_t, int64_t, const cplx<T>*, \
+                                  int, hipStream_t);                                                       \
+    template void launch_col_fft<T>(int, int, bool, const cplx<T>*, cplx<T>*, const ColGeom&, const cplx<T>*, \
+                                    int, hipStream_t);                                                     \
+    template void launch_z_fused<T>(int, int, const cplx<T>*, cplx<T>*, const T*, const ZGeom&, const cplx<T>*, \
+                                    int, hipStream_t);
 INSTANTIATE(float)
 INSTANTIATE(double)
 #undef INSTANTIATE

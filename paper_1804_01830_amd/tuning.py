@@ -39,12 +39,14 @@ def _write(path, data):
 
 
 def to_dict(t):
-    return {"rows_x": t.rows_x, "tk_y": t.tk_y, "tk_z": t.tk_z, "ms": [round(float(v), 5) for v in t.ms]}
+    return {"rows_x": t.rows_x, "tk_y": t.tk_y, "tk_z": t.tk_z, "ex": t.ex, "ey": t.ey, "ez": t.ez,
+            "ms": [round(float(v), 5) for v in t.ms]}
 
 
 def from_dict(d):
     t = B.Tuning()
     t.rows_x, t.tk_y, t.tk_z = int(d["rows_x"]), int(d["tk_y"]), int(d["tk_z"])
+    t.ex, t.ey, t.ez = int(d.get("ex", 0)), int(d.get("ey", 0)), int(d.get("ez", 0))
     for i, v in enumerate(d.get("ms", [0, 0, 0])[:3]):
         t.ms[i] = float(v)
     return t
