@@ -228,6 +228,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes for the FP32 plan")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a device buffer of this many MiB once (a plain copy kernel of "
+                         "known size, for scaling hardware traffic counters)")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-pool", type=int, default=4)
@@ -326,6 +329,14 @@ def main():
     if base is not None:
         line["cpu_baseline"] = base
         line["error_vs_oracle"] = errors_at(tg, ref, r32["out"], r64["out"])
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calib_copy_bytes"] = 4 * n
     print(json.dumps(line), flush=True)
 
 

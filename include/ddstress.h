@@ -84,8 +84,12 @@ typedef struct {
     int32_t batch;         /* B >= 1 densities per stress() call sharing this plan */
     int32_t near_shells;   /* S: a cell offset D is subdivided when |D_a| d_a <= S max(d) on every
                               axis; 0 selects the default 2, negative is invalid */
-    uint32_t flags;        /* must be 0 */
+    uint32_t flags;        /* 0 or DDSTRESS_FLAG_FULL_SPECTRUM */
 } ddstress_desc;
+
+/* Store the kernel spectrum for every wavevector even where a mirror symmetry
+ * would let half of it be reconstructed (see ddstress_info.mirror_y). */
+#define DDSTRESS_FLAG_FULL_SPECTRUM 4u
 
 /* Read-only facts about a plan. */
 typedef struct {
@@ -98,6 +102,10 @@ typedef struct {
     int32_t tile_y;        /* columns per block of the y passes */
     int32_t rows_x;        /* rows per block of the x passes */
     int32_t ex, ey, ez;    /* element classes of the x, y and fused z passes (see ddstress_tuning) */
+    int32_t mirror_y;      /* 1: every coefficient plane is even or odd under y -> -y (each line direction
+                              has t_y = 0 or is parallel to e_y), so the spectrum is kept for ky <= Py/2
+                              only, with a sign per plane for the mirrored rows */
+    int32_t mirror_z;      /* the same for z -> -z and kz <= Pz/2 */
     size_t  cached_bytes;  /* device bytes held for the plan's lifetime (kernel spectrum, tables) */
     size_t  work_bytes;    /* device bytes of per-call work buffers */
     double  kernel_real_max;  /* max |Re K^| over the spectrum: zero up to rounding (K is odd) */
@@ -106,8 +114,8 @@ typedef struct {
 
 /* Launch shapes of the passes: a tuning choice. A transform of length N runs
  * with E = min(N, e) elements per thread and radices <= E, where the element
- * class e is 8 or 16 for the x and y passes and 4 or 8 (FP32) / 2 or 4 (FP64)
- * for the fused z pass; 0 selects the default. Tile sizes change which
+ * class e is 8 or 16 for the x and y passes and 4 (FP32) / 2 (FP64) for the
+ * fused z pass; 0 selects the default. Tile sizes change which
  * threads do the work, not the arithmetic (bit-identical results); element
  * classes change the radix sequence and hence the rounding (within the
  * stated tolerances). */
@@ -119,7 +127,9 @@ typedef struct {
     float   ms[3];         /* autotune: median device ms of the chosen x pair, y pair and z pass */
 } ddstress_tuning;
 
-/* Device bytes a plan for `desc` will hold: `cached_bytes` for its lifetime,
+/* Device bytes a plan for `desc` will hold (with the mirror symmetries the
+ * line directions predict; a plan whose coefficients fail the numerical parity
+ * check keeps the full spectrum and holds more): `cached_bytes` for its lifetime,
  * `work_bytes` for its per-call buffers, `build_bytes` transiently during
  * ddstress_plan_create. Any output pointer may be NULL. Synchronous, no
  * device work. Returns DDSTRESS_E_INVALID for an invalid descriptor. */

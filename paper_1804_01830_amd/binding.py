@@ -12,6 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libddstress.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = range(6)
+FLAG_FULL_SPECTRUM = 4
 HOST, DEVICE_COPY, DEVICE_BORROW = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STATE", 5: "E_UNSUPPORTED"}
 
@@ -40,7 +41,8 @@ class Info(ctypes.Structure):
     _fields_ = [("padded", ctypes.c_int32 * 3), ("subdiv", ctypes.c_int32 * 3), ("channels", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("precision", ctypes.c_int32), ("tile_z", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("rows_x", ctypes.c_int32), ("ex", ctypes.c_int32),
-                ("ey", ctypes.c_int32), ("ez", ctypes.c_int32),
+                ("ey", ctypes.c_int32), ("ez", ctypes.c_int32), ("mirror_y", ctypes.c_int32),
+                ("mirror_z", ctypes.c_int32),
                 ("cached_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t),
                 ("kernel_real_max", ctypes.c_double), ("kernel_imag_max", ctypes.c_double)]
 

@@ -84,6 +84,9 @@ struct Shape {
     int C, B, L;
     int elem;        // bytes per real
     int tkz, ntz;    // fused z tile and number of kx tiles
+    bool mir_y, mir_z;          // spectrum kept for ky <= Py/2 (kz <= Pz/2) only, by mirror parity
+    int nkys, nkzs;             // spectrum rows kept along ky and kz
+    uint64_t sgn_y, sgn_z;      // bit c*6+v: S_{v,c} odd under ky -> -ky (kz -> -kz)
     int64_t cells() const { return (int64_t)N[0] * N[1] * N[2]; }
     int64_t padded() const { return (int64_t)P[0] * P[1] * P[2]; }
 };
@@ -106,7 +109,29 @@ void validate(const ddstress_desc* d) {
     if (d->precision != 32 && d->precision != 64) fail(DDSTRESS_E_INVALID, "precision must be 32 or 64");
     if (d->batch < 1) fail(DDSTRESS_E_INVALID, "batch must be >= 1");
     if (d->near_shells < 0) fail(DDSTRESS_E_INVALID, "near_shells must be >= 0");
-    if (d->flags != 0) fail(DDSTRESS_E_UNSUPPORTED, "flags must be 0");
+    if ((d->flags & ~DDSTRESS_FLAG_FULL_SPECTRUM) != 0) fail(DDSTRESS_E_UNSUPPORTED, "unknown flag bits");
+}
+
+// A mirror a -> -a maps every line segment onto itself (possibly reversed)
+// when each line direction has t_a = 0 or is parallel to e_a; then every
+// coefficient plane is even or odd under that mirror (checked numerically
+// when the plan is built).
+bool predict_mirror(const ddstress_desc* d, int axis) {
+    if (d->flags & DDSTRESS_FLAG_FULL_SPECTRUM) return false;
+    for (int l = 0; l < d->n_lines; ++l) {
+        const double* t = d->t[l];
+        const bool perp = t[axis] == 0.0;
+        const bool along = t[(axis + 1) % 3] == 0.0 && t[(axis + 2) % 3] == 0.0;
+        if (!perp && !along) return false;
+    }
+    return true;
+}
+
+void set_mirrors(Shape& s, bool my, bool mz) {
+    s.mir_y = my && s.P[1] >= 2;
+    s.mir_z = mz && s.P[2] >= 2;
+    s.nkys = s.mir_y ? s.P[1] / 2 + 1 : s.P[1];
+    s.nkzs = s.mir_z ? s.P[2] / 2 + 1 : s.P[2];
 }
 
 Shape make_shape(const ddstress_desc* d) {
@@ -124,11 +149,13 @@ Shape make_shape(const ddstress_desc* d) {
     s.elem = d->precision == 32 ? 4 : 8;
     s.tkz = default_z_tk(s.P[2], s.elem);
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
+    set_mirrors(s, predict_mirror(d, 1), predict_mirror(d, 2));
+    s.sgn_y = s.sgn_z = 0;
     return s;
 }
 
 size_t spec_bytes(const Shape& s) {
-    return (size_t)s.P[1] * s.ntz * s.C * 6 * (size_t)s.P[2] * s.tkz * s.elem;
+    return (size_t)s.nkys * s.ntz * s.C * 6 * (size_t)s.nkzs * s.tkz * s.elem;
 }
 size_t twiddle_bytes(const Shape& s) { return (size_t)kTwiddleEntries * 2 * s.elem; }
 // complex elements of the two ping-pong work buffers
@@ -218,14 +245,60 @@ struct ddstress_plan_s {
 
 namespace {
 
+// Plan build, FP64 throughout: (1) when a mirror symmetry is predicted, the
+// coefficients of every line are evaluated once and the parity of each of
+// their planes under y -> -y and z -> -z is measured; the kept spectrum rows
+// and the signs follow (a plane without a definite parity cancels the
+// compression along that axis); (2) per line, the coefficients are evaluated,
+// transformed (x real-to-complex, y, z) and the imaginary part of the kept
+// rows is stored in the plan precision.
 template <typename T>
 void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
-    const Shape& s = p->shape;
-    DevBuf kr, kc, tw64, maxbits;
+    Shape& s = p->shape;
+    DevBuf kr, kc, tw64, maxbits, stats;
     kr.alloc(build_real_bytes(s), "kernel coefficients");
+    maxbits.alloc(2 * sizeof(unsigned long long), "spectrum check");
+    if (s.mir_y || s.mir_z) {
+        const size_t nstat = (size_t)s.L * 18 * 5;
+        stats.alloc(nstat * sizeof(unsigned long long), "mirror statistics");
+        check_hip(hipMemsetAsync(stats.p, 0, stats.bytes, st), "clear mirror statistics");
+        for (int l = 0; l < s.L; ++l) {
+            KernelParams kp = make_kernel_params(p->desc, l, s.P);
+            launch_kernel_build(kp, kr.as<double>(), st);
+            launch_mirror_stats(kr.as<double>(), s.P, stats.as<unsigned long long>() + (size_t)l * 90, st);
+        }
+        std::vector<unsigned long long> hs(nstat);
+        check_hip(hipMemcpyAsync(hs.data(), stats.p, nstat * sizeof(unsigned long long), hipMemcpyDeviceToHost, st),
+                  "mirror statistics readback");
+        check_hip(hipStreamSynchronize(st), "mirror statistics");
+        bool ok_y = s.mir_y, ok_z = s.mir_z;
+        uint64_t sy = 0, sz = 0;
+        for (int l = 0; l < s.L; ++l)
+            for (int q = 0; q < 18; ++q) {          // q = gamma * 6 + v
+                double v[5];
+                for (int e = 0; e < 5; ++e) std::memcpy(&v[e], &hs[((size_t)l * 18 + q) * 5 + e], sizeof(double));
+                const double tol = 1e-13 * v[4];
+                const int bit = (3 * l + q / 6) * 6 + q % 6;
+                if (v[0] <= tol) {
+                } else if (v[1] <= tol) {
+                    sy |= 1ull << bit;
+                } else {
+                    ok_y = false;
+                }
+                if (v[2] <= tol) {
+                } else if (v[3] <= tol) {
+                    sz |= 1ull << bit;
+                } else {
+                    ok_z = false;
+                }
+            }
+        set_mirrors(s, ok_y, ok_z);
+        s.sgn_y = ok_y ? sy : 0;
+        s.sgn_z = ok_z ? sz : 0;
+    }
+    p->spec->alloc(spec_bytes(s), "kernel spectrum");
     kc.alloc(build_cplx_bytes(s), "kernel transform");
     tw64.alloc((size_t)kTwiddleEntries * sizeof(cplx<double>), "FP64 twiddles");
-    maxbits.alloc(2 * sizeof(unsigned long long), "spectrum check");
     std::vector<cplx<double>> host(kTwiddleEntries);
     fill_twiddles<double>(host.data());
     check_hip(hipMemcpyAsync(tw64.p, host.data(), host.size() * sizeof(cplx<double>), hipMemcpyHostToDevice, st),
@@ -243,8 +316,7 @@ void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
         launch_kernel_build(kp, kr.as<double>(), st);
         // x: 18 * Pz * Py rows of Px reals (no padding: the coefficients fill the grid)
         launch_x_r2c<double>(s.M, default_ev_col(s.M), kr.as<double>(), kc.as<cplx<double>>(),
-                             18LL * s.P[2] * s.P[1], s.P[0],
-                             s.P[0], s.wx, tw, rows, st);
+                             18LL * s.P[2] * s.P[1], s.P[0], s.P[0], s.wx, tw, rows, st);
         ColGeom gy{};
         gy.ncols = s.M1;
         gy.n_in = s.P[1];
@@ -267,8 +339,8 @@ void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
         gz.ips = gz.ops = plane_c;
         launch_col_fft<double>(s.P[2], default_ev_col(s.P[2]), true, kc.as<cplx<double>>(), kc.as<cplx<double>>(),
                                gz, tw, tkz, st);
-        launch_extract<T>(kc.as<cplx<double>>(), p->spec->as<T>(), l, s.C, s.M1, s.wx, s.P[1], s.P[2], s.tkz,
-                          s.ntz, inv_p, maxbits.as<unsigned long long>(), st);
+        launch_extract<T>(kc.as<cplx<double>>(), p->spec->as<T>(), l, s.C, s.M1, s.wx, s.P[1], s.P[2], s.nkys, s.nkzs,
+                          s.tkz, s.ntz, inv_p, maxbits.as<unsigned long long>(), st);
     }
     unsigned long long bits[2] = {0, 0};
     check_hip(hipMemcpyAsync(bits, maxbits.p, sizeof(bits), hipMemcpyDeviceToHost, st), "spectrum check readback");
@@ -318,6 +390,10 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     p->mark(st);
     // z forward + contraction + z inverse
     ZGeom gz{};
+    gz.nky_s = s.nkys;
+    gz.nkz_s = s.nkzs;
+    gz.sgn_y = s.sgn_y;
+    gz.sgn_z = s.sgn_z;
     gz.ncols = s.M1;
     gz.ntiles = s.ntz;
     gz.nky = Py;
@@ -450,7 +526,6 @@ void create_plan(const ddstress_desc* desc, const ddstress_tuning* tuning, hipSt
         const Shape& s = p->shape;
         p->spec = std::make_shared<DevBuf>();
         p->tw = std::make_shared<DevBuf>();
-        p->spec->alloc(spec_bytes(s), "kernel spectrum");
         p->tw->alloc(twiddle_bytes(s), "twiddles");
         p->work1.alloc((size_t)work1_elems(s) * 2 * s.elem, "work buffer 1");
         p->work2.alloc((size_t)work2_elems(s) * 2 * s.elem, "work buffer 2");
@@ -504,7 +579,7 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
     Shape s = make_shape(desc);
     const int64_t BC = (int64_t)s.B * s.C, B6 = (int64_t)s.B * 6;
     const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2], Py = s.P[1], Pz = s.P[2];
-    const std::vector<int> zev = s.elem == 4 ? std::vector<int>{4, 8} : std::vector<int>{2, 4};
+    const std::vector<int> zev = {default_ev_z(s.elem)};
     std::vector<std::pair<int, int>> zlist;     // (tk, ev)
     for (int ev : zev)
         for (int tk = 1; tk <= 256; tk *= 2)
@@ -568,6 +643,7 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
     for (auto& z : zlist) {
         const int tk = z.first, ev = z.second;
         ZGeom gz{};
+        gz.nky_s = s.nkys; gz.nkz_s = s.nkzs;
         gz.ncols = s.M1; gz.ntiles = (s.M1 + tk - 1) / tk; gz.nky = Py; gz.nz = Nz; gz.C = s.C; gz.B = s.B;
         gz.irs = (int64_t)Py * s.wx; gz.iqs = (int64_t)Nz * Py * s.wx; gz.ios = s.wx;
         gz.ors = gz.irs; gz.oqs = gz.iqs; gz.oos = gz.ios;
@@ -676,8 +752,14 @@ ddstress_status ddstress_plan_share(ddstress_plan src, int32_t batch, ddstress_p
             p->desc = src->desc;
             p->desc.batch = batch;
             p->shape = make_shape(&p->desc);
-            p->shape.tkz = src->shape.tkz;      // the shared spectrum's tile layout
+            p->shape.tkz = src->shape.tkz;      // the shared spectrum's layout
             p->shape.ntz = src->shape.ntz;
+            p->shape.mir_y = src->shape.mir_y;
+            p->shape.mir_z = src->shape.mir_z;
+            p->shape.nkys = src->shape.nkys;
+            p->shape.nkzs = src->shape.nkzs;
+            p->shape.sgn_y = src->shape.sgn_y;
+            p->shape.sgn_z = src->shape.sgn_z;
             p->spec = src->spec;
             p->tw = src->tw;
             p->rows_x = src->rows_x;
@@ -728,6 +810,8 @@ ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info) 
         info->tile_z = s.tkz;
         info->tile_y = plan->tk_y;
         info->rows_x = plan->rows_x;
+        info->mirror_y = s.mir_y ? 1 : 0;
+        info->mirror_z = s.mir_z ? 1 : 0;
         info->ex = plan->ex;
         info->ey = plan->ey;
         info->ez = plan->ez;

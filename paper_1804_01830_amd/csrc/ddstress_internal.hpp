@@ -62,6 +62,8 @@ void launch_col_fft(int N, int ev, bool forward, const cplx<T>* in, cplx<T>* out
                     const cplx<T>* tw, int tk, hipStream_t s);
 // Fused forward z transform, contraction with the kernel spectrum and inverse z.
 struct ZGeom {
+    int nky_s, nkz_s;      // spectrum rows kept along ky and kz (Py or Py/2+1, Pz or Pz/2+1)
+    uint64_t sgn_y, sgn_z; // bit c*6+v set: S_{v,c} is odd under ky -> -ky (resp. kz -> -kz)
     int ncols;             // valid kx columns
     int ntiles;            // kx tiles (ncols rounded up to tk)
     int nky;               // ky rows (blocks along y)
@@ -102,10 +104,13 @@ struct KernelParams {
 KernelParams make_kernel_params(const ddstress_desc& desc, int line, const int P[3]);
 // 18 planes [gamma][v][Pz][Py][Px] of FP64 coefficients.
 void launch_kernel_build(const KernelParams& p, double* out, hipStream_t s);
-// Spectrum extraction: S[ky][tile][c][v][kz][tk] = Im(Khat) / P for channels 3*line..3*line+2.
+// Mirror parity statistics of the 18 planes (see k_mirror_stats): 90 values.
+void launch_mirror_stats(const double* kr, const int P[3], unsigned long long* stats, hipStream_t s);
+// Spectrum extraction: S[kyc][tile][c][v][kzc][tk] = Im(Khat) / P for channels 3*line..3*line+2,
+// kyc < nky, kzc < nkz.
 template <typename T>
-void launch_extract(const cplx<double>* kh, T* spec, int line, int C, int ncols, int64_t wx, int Py,
-                    int Pz, int tk, int ntiles, double inv_p, unsigned long long* maxbits,
+void launch_extract(const cplx<double>* kh, T* spec, int line, int C, int ncols, int64_t wx, int Py, int Pz,
+                    int nky, int nkz, int tk, int ntiles, double inv_p, unsigned long long* maxbits,
                     hipStream_t s);
 
 }  // namespace dds

@@ -100,6 +100,40 @@ __device__ __forceinline__ void dftR(cplx<T>* v) {
 
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
+// Raw buffer loads: a 128-bit resource (base, byte size) kept in scalar
+// registers, a per-lane 32-bit byte offset and a wave-uniform byte offset.
+// Reads at or beyond the resource's size return zero.
+constexpr int kBufferFlags = 0x00020000;   // raw (untyped) dword access on gfx9-family targets
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferFlags);
+}
+
+template <typename T>
+__device__ __forceinline__ T buf_real(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ float buf_real<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_real<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return __hiloint2double((int)v[1], (int)v[0]);
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> buf_cplx(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ cplx<float> buf_cplx<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return {__uint_as_float(v[0]), __uint_as_float(v[1])};
+}
+template <>
+__device__ __forceinline__ cplx<double> buf_cplx<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    return {__hiloint2double((int)v[1], (int)v[0]), __hiloint2double((int)v[3], (int)v[2])};
+}
+
 // Elements per thread used for a transform of length N in the plain passes.
 constexpr int elems_for(int N) { return N <= 8 ? N : (N <= 64 ? 8 : 16); }
 // Elements per thread in the fused z kernel (six complex accumulators per

@@ -92,13 +92,14 @@ __device__ __forceinline__ bool wrap_offset(int i, int n, int P, int& off) {
     return false;
 }
 
-__global__ void __launch_bounds__(256) k_kernel_build(double* __restrict__ out, KernelParams kp,
-                                                      int64_t plane) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= plane) return;
-    const int ix = (int)(idx % kp.P[0]);
-    const int iy = (int)((idx / kp.P[0]) % kp.P[1]);
-    const int iz = (int)(idx / ((int64_t)kp.P[0] * kp.P[1]));
+// One thread per (x, y) point of one z plane of the padded grid: blockIdx.y
+// and blockIdx.z carry the y and z indices, so no 64-bit division is needed.
+__global__ void __launch_bounds__(256) k_kernel_build(double* __restrict__ out, KernelParams kp, int64_t plane) {
+    const int ix = blockIdx.x * blockDim.x + threadIdx.x;
+    const int iy = blockIdx.y;
+    const int iz = blockIdx.z;
+    if (ix >= kp.P[0]) return;
+    const int64_t idx = ((int64_t)iz * kp.P[1] + iy) * kp.P[0] + ix;
     double acc[18];
     for (int q = 0; q < 18; ++q) acc[q] = 0.0;
     int D[3];
@@ -127,40 +128,83 @@ __global__ void __launch_bounds__(256) k_kernel_build(double* __restrict__ out, 
     for (int q = 0; q < 18; ++q) out[q * plane + idx] = acc[q];
 }
 
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* a, double v) {
+    // non-negative doubles order like their bit patterns
+    atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+// Mirror parity of the 18 coefficient planes: for each plane q and mirror
+// axis a (0: y -> -y, 1: z -> -z), max |K - K'| and max |K + K'| with K' the
+// value at the mirrored offset, and max |K|. stats[q*5 + {0,1,2,3,4}] =
+// {even_y, odd_y, even_z, odd_z, max}. One thread per (x, y, z) point.
+__global__ void __launch_bounds__(256) k_mirror_stats(const double* __restrict__ kr, int Px, int Py, int Pz,
+                                                      int64_t plane, unsigned long long* __restrict__ stats) {
+    const int ix = blockIdx.x * blockDim.x + threadIdx.x;
+    const int iy = blockIdx.y;
+    const int iz = blockIdx.z;
+    const bool ok = ix < Px;
+    const int my = (Py - iy) & (Py - 1);
+    const int mz = (Pz - iz) & (Pz - 1);
+    const int64_t i0 = ((int64_t)iz * Py + iy) * Px + (ok ? ix : 0);
+    const int64_t iyv = ((int64_t)iz * Py + my) * Px + (ok ? ix : 0);
+    const int64_t izv = ((int64_t)mz * Py + iy) * Px + (ok ? ix : 0);
+    __shared__ double red[5][256];
+    for (int q = 0; q < 18; ++q) {
+        double v[5] = {0, 0, 0, 0, 0};
+        if (ok) {
+            const double k = kr[q * plane + i0];
+            const double ky = kr[q * plane + iyv];
+            const double kz = kr[q * plane + izv];
+            v[0] = fabs(k - ky);
+            v[1] = fabs(k + ky);
+            v[2] = fabs(k - kz);
+            v[3] = fabs(k + kz);
+            v[4] = fabs(k);
+        }
+        for (int e = 0; e < 5; ++e) red[e][threadIdx.x] = v[e];
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                for (int e = 0; e < 5; ++e) red[e][threadIdx.x] = fmax(red[e][threadIdx.x], red[e][threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            for (int e = 0; e < 5; ++e) atomic_max_nonneg(&stats[q * 5 + e], red[e][0]);
+        __syncthreads();
+    }
+}
+
+// Spectrum extraction: S = Im(K^) / P for the channels 3*line .. 3*line+2,
+// stored as [kyc][tile][c][v][kzc][tk] for kyc < nky, kzc < nkz (the kept
+// halves when a mirror symmetry lets the rest be reconstructed). One thread
+// per (kx in the tiled range, kyc, kzc), looping over the 18 planes; also the
+// maxima of |Re K^| and |Im K^| over the kept entries.
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract(const cplx<double>* __restrict__ kh, T* __restrict__ spec,
-                                                 int line, int C, int ncols, int64_t wx, int Py, int Pz,
-                                                 int tk, int ntiles, double inv_p,
+                                                 int line, int C, int ncols, int64_t wx, int Py, int Pz, int nky,
+                                                 int nkz, int tk, int ntiles, double inv_p,
                                                  unsigned long long* __restrict__ maxbits) {
-    // one thread per (gamma, v, kz, ky, column of the tiled kx range)
-    const int64_t kxr = (int64_t)ntiles * tk;
-    const int64_t total = 18LL * Pz * Py * kxr;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int kx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ky = blockIdx.y;
+    const int kz = blockIdx.z;
+    const int kxr = ntiles * tk;
     double re = 0.0, im = 0.0;
-    if (idx < total) {
-        const int64_t kx = idx % kxr;
-        int64_t r = idx / kxr;
-        const int ky = (int)(r % Py);
-        r /= Py;
-        const int kz = (int)(r % Pz);
-        const int gv = (int)(r / Pz);          // gamma * 6 + v
-        const int g = gv / 6, v = gv % 6;
-        if (kx < ncols) {
-            const cplx<double> val = kh[(((int64_t)gv * Pz + kz) * Py + ky) * wx + kx];
-            re = fabs(val.x);
-            im = fabs(val.y);
-            const int tile = (int)(kx / tk), col = (int)(kx % tk);
+    if (kx < kxr) {
+        const int tile = kx / tk, col = kx % tk;
+        for (int gv = 0; gv < 18; ++gv) {
+            const int g = gv / 6, v = gv % 6;
             const int ch = 3 * line + g;
-            const int64_t o = (((((int64_t)ky * ntiles + tile) * C + ch) * 6 + v) * Pz + kz) * tk + col;
-            spec[o] = (T)(val.y * inv_p);
-        } else {
-            const int tile = (int)(kx / tk), col = (int)(kx % tk);
-            const int ch = 3 * line + g;
-            const int64_t o = (((((int64_t)ky * ntiles + tile) * C + ch) * 6 + v) * Pz + kz) * tk + col;
-            spec[o] = T(0);
+            const int64_t o = (((((int64_t)ky * ntiles + tile) * C + ch) * 6 + v) * nkz + kz) * tk + col;
+            if (kx < ncols) {
+                const cplx<double> val = kh[(((int64_t)gv * Pz + kz) * Py + ky) * wx + kx];
+                re = fmax(re, fabs(val.x));
+                im = fmax(im, fabs(val.y));
+                spec[o] = (T)(val.y * inv_p);
+            } else {
+                spec[o] = T(0);
+            }
         }
     }
-    // block maxima of |Re| and |Im| (non-negative doubles order like their bit patterns)
     __shared__ double sre[256], sim[256];
     sre[threadIdx.x] = re;
     sim[threadIdx.x] = im;
@@ -173,8 +217,8 @@ __global__ void __launch_bounds__(256) k_extract(const cplx<double>* __restrict_
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        atomicMax(&maxbits[0], (unsigned long long)__double_as_longlong(sre[0]));
-        atomicMax(&maxbits[1], (unsigned long long)__double_as_longlong(sim[0]));
+        atomic_max_nonneg(&maxbits[0], sre[0]);
+        atomic_max_nonneg(&maxbits[1], sim[0]);
     }
 }
 
@@ -216,25 +260,32 @@ KernelParams make_kernel_params(const ddstress_desc& desc, int line, const int P
 
 void launch_kernel_build(const KernelParams& kp, double* out, hipStream_t s) {
     const int64_t plane = (int64_t)kp.P[0] * kp.P[1] * kp.P[2];
-    const int64_t blocks = (plane + 255) / 256;
-    hipLaunchKernelGGL(k_kernel_build, dim3((unsigned)blocks), dim3(256), 0, s, out, kp, plane);
+    const dim3 grid((unsigned)((kp.P[0] + 255) / 256), (unsigned)kp.P[1], (unsigned)kp.P[2]);
+    hipLaunchKernelGGL(k_kernel_build, grid, dim3(256), 0, s, out, kp, plane);
     check_hip(hipGetLastError(), "kernel build launch");
 }
 
+void launch_mirror_stats(const double* kr, const int P[3], unsigned long long* stats, hipStream_t s) {
+    const int64_t plane = (int64_t)P[0] * P[1] * P[2];
+    const dim3 grid((unsigned)((P[0] + 255) / 256), (unsigned)P[1], (unsigned)P[2]);
+    hipLaunchKernelGGL(k_mirror_stats, grid, dim3(256), 0, s, kr, P[0], P[1], P[2], plane, stats);
+    check_hip(hipGetLastError(), "mirror statistics launch");
+}
+
 template <typename T>
-void launch_extract(const cplx<double>* kh, T* spec, int line, int C, int ncols, int64_t wx, int Py,
-                    int Pz, int tk, int ntiles, double inv_p, unsigned long long* maxbits,
+void launch_extract(const cplx<double>* kh, T* spec, int line, int C, int ncols, int64_t wx, int Py, int Pz,
+                    int nky, int nkz, int tk, int ntiles, double inv_p, unsigned long long* maxbits,
                     hipStream_t s) {
-    const int64_t total = 18LL * Pz * Py * (int64_t)ntiles * tk;
-    const int64_t blocks = (total + 255) / 256;
-    hipLaunchKernelGGL((k_extract<T>), dim3((unsigned)blocks), dim3(256), 0, s, kh, spec, line, C, ncols,
-                       wx, Py, Pz, tk, ntiles, inv_p, maxbits);
+    const int kxr = ntiles * tk;
+    const dim3 grid((unsigned)((kxr + 255) / 256), (unsigned)nky, (unsigned)nkz);
+    hipLaunchKernelGGL((k_extract<T>), grid, dim3(256), 0, s, kh, spec, line, C, ncols, wx, Py, Pz, nky, nkz, tk,
+                       ntiles, inv_p, maxbits);
     check_hip(hipGetLastError(), "spectrum extraction launch");
 }
 
-template void launch_extract<float>(const cplx<double>*, float*, int, int, int, int64_t, int, int, int,
+template void launch_extract<float>(const cplx<double>*, float*, int, int, int, int64_t, int, int, int, int, int,
                                     int, double, unsigned long long*, hipStream_t);
-template void launch_extract<double>(const cplx<double>*, double*, int, int, int, int64_t, int, int, int,
+template void launch_extract<double>(const cplx<double>*, double*, int, int, int, int64_t, int, int, int, int, int,
                                      int, double, unsigned long long*, hipStream_t);
 
 template <typename T>

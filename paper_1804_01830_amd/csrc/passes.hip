@@ -162,6 +162,10 @@ __global__ void __launch_bounds__(512) k_col_fft(const cplx<T>* in, cplx<T>* out
 // in registers with a fixed channel order, and transforms each back along z,
 // writing the first nz rows. The spectrum tile of the block is stored
 // contiguously as [c][v][kz][tk].
+// The loads are software-pipelined: the density column and the spectrum
+// values of the next channel (or of the next realisation's first channel) are
+// requested before the current transform, whose barriers do not wait for
+// global loads, so their latency overlaps the FFT work.
 // ----------------------------------------------------------------------------
 template <typename T, int N, int E>
 __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
@@ -179,10 +183,52 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
     const int colc = valid ? col : 0;
     const ColMajor lay{tk};
     const cplx<T>* twN = tw + (N - 1);
-    const int irs = (int)g.irs, ors = (int)g.ors;    // in-block offsets fit in 32 bits
-    const T* sp = spec + ((int64_t)ky * g.ntiles + tile) * (int64_t)g.C * 6 * N * tk + c;
-    const cplx<T>* in_b = in + (int64_t)ky * g.ios + colc;
+    const int ors = (int)g.ors;                      // in-block offsets fit in 32 bits
+    // Spectrum tile of this block: [c][v][kzc][tk] at row kyc. With a y mirror
+    // only ky <= Py/2 is stored and row Py - ky stands in for ky > Py/2; with a
+    // z mirror only kz <= N/2 is stored and elements m >= E/2 (kz >= N/2) read
+    // kz' = N - kz = (Tc - j) + Tc (E - 1 - m). Odd planes change sign.
+    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
+    const int kyc = flip_y ? g.nky - ky : ky;
+    const bool zc = g.nkz_s < N;
+    const int nkz = g.nkz_s;
+    const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * tk;
+    const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * tk * sizeof(T)));
+    const int s_lane = (j * tk + c) * (int)sizeof(T);
+    const int s_lane_m = ((Tc - j) * tk + c) * (int)sizeof(T);
+    // density planes: rows z < nz of the block's columns; rows >= nz lie beyond the resource (read as zero)
+    const cplx<T>* in_b = in + (int64_t)ky * g.ios + (int64_t)tile * tk;
+    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
+    // lanes of padding columns (col >= ncols) read the tile's first column, which is valid
+    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
+    const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
     cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
+
+#define DDS_LOAD_RHO(DST, BB, CH)                                                          \
+    {                                                                                      \
+        const __amdgpu_buffer_rsrc_t rr_ = make_rsrc(in_b + (int64_t)((BB) * g.C + (CH)) * g.iqs, plane_bytes); \
+        _Pragma("unroll") for (int m = 0; m < E; ++m) DST[m] = buf_cplx<T>(rr_, r_lane, m * r_step); \
+    }
+#define DDS_LOAD_SPEC(DST, CH)                                                             \
+    {                                                                                      \
+        _Pragma("unroll") for (int v = 0; v < 6; ++v) {                                    \
+            const int bit_ = (CH) * 6 + v;                                                 \
+            const T sy_ = (flip_y && ((g.sgn_y >> bit_) & 1)) ? T(-1) : T(1);              \
+            const T sz_ = ((g.sgn_z >> bit_) & 1) ? -sy_ : sy_;                            \
+            const int base_ = bit_ * nkz;                                                  \
+            _Pragma("unroll") for (int m = 0; m < E; ++m) {                                \
+                if (!zc || 2 * m < E)                                                      \
+                    DST[v][m] = sy_ * buf_real<T>(srs, s_lane, (base_ + Tc * m) * tk * (int)sizeof(T)); \
+                else                                                                       \
+                    DST[v][m] = sz_ * buf_real<T>(srs, s_lane_m, (base_ + Tc * (E - 1 - m)) * tk * (int)sizeof(T)); \
+            }                                                                              \
+        }                                                                                  \
+    }
+
+    cplx<T> cur[E], nxt[E];
+    T sv[6][E];
+    DDS_LOAD_RHO(cur, 0, 0)
+    DDS_LOAD_SPEC(sv, 0)
     for (int b = 0; b < g.B; ++b) {
         cplx<T> acc[6][E];
 #pragma unroll
@@ -190,24 +236,28 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
 #pragma unroll
             for (int m = 0; m < E; ++m) acc[v][m] = {T(0), T(0)};
         for (int ch = 0; ch < g.C; ++ch) {
-            const cplx<T>* src = in_b + (int64_t)(b * g.C + ch) * g.iqs;
-            cplx<T> reg[E];
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const int z = j + Tc * m;
-                reg[m] = (valid && z < g.nz) ? src[z * irs] : cplx<T>{T(0), T(0)};
-            }
-            fft_regs<T, N, E, true>(reg, lds, lay, c, j, twN);
-            const T* spc = sp + (int64_t)ch * 6 * N * tk + j * tk;
+            const bool more = ch + 1 < g.C;
+            if (more) DDS_LOAD_RHO(nxt, b, ch + 1)
+            fft_regs<T, N, E, true>(cur, lds, lay, c, j, twN);
 #pragma unroll
             for (int v = 0; v < 6; ++v)
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
-                    const T s = spc[(v * N + Tc * m) * tk];
-                    acc[v][m].x -= s * reg[m].y;
-                    acc[v][m].y += s * reg[m].x;
+                    acc[v][m].x -= sv[v][m] * cur[m].y;
+                    acc[v][m].y += sv[v][m] * cur[m].x;
                 }
+            if (more) {
+                DDS_LOAD_SPEC(sv, ch + 1)
+#pragma unroll
+                for (int m = 0; m < E; ++m) cur[m] = nxt[m];
+            }
         }
+        if (b + 1 < g.B) {      // first channel of the next realisation
+            DDS_LOAD_RHO(cur, b + 1, 0)
+            DDS_LOAD_SPEC(sv, 0)
+        }
+#undef DDS_LOAD_RHO
+#undef DDS_LOAD_SPEC
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             fft_regs<T, N, E, false>(acc[v], lds, lay, c, j, twN);
@@ -227,16 +277,18 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
 // Launch geometry and dispatch. A transform of length N runs with
 // E = min(N, ev) elements per thread, where the element class ev is a tuning
 // choice (it also bounds the radix, R <= E): 8 or 16 for the x and y passes;
-// 4 or 8 (FP32), 2 or 4 (FP64) for the fused z pass.
+// 4 (FP32) or 2 (FP64) for the fused z pass, which keeps six accumulators,
+// the next channel's spectrum values and density column per element in
+// registers (larger classes spill).
 // ----------------------------------------------------------------------------
 static int ecount(int N, int ev) { return N < ev ? N : ev; }
 int x_threads(int M, int rows, int ev) { return rows * (M / ecount(M, ev)); }
 int col_threads(int N, int tk, int ev) { return tk * (N / ecount(N, ev)); }
 int z_threads(int N, int tk, int ev) { return tk * (N / ecount(N, ev)); }
 int default_ev_col(int N) { return N <= 64 ? 8 : 16; }
-int default_ev_z(int elem_bytes) { return elem_bytes <= 4 ? 8 : 4; }
+int default_ev_z(int elem_bytes) { return elem_bytes <= 4 ? 4 : 2; }
 bool ev_col_ok(int ev) { return ev == 8 || ev == 16; }
-bool ev_z_ok(int ev, int elem_bytes) { return elem_bytes <= 4 ? (ev == 4 || ev == 8) : (ev == 2 || ev == 4); }
+bool ev_z_ok(int ev, int elem_bytes) { return elem_bytes <= 4 ? ev == 4 : ev == 2; }
 
 int default_col_tk(int N, int elem_bytes) {
     const int tc = N / ecount(N, default_ev_col(N));
@@ -384,13 +436,10 @@ void launch_z_fused(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spe
     const int64_t blocks = (int64_t)g.ntiles * g.nky;
     if (blocks <= 0) return;
     if (!ev_z_ok(ev, (int)sizeof(T))) fail(DDSTRESS_E_INVALID, "z element class not supported for this precision");
-    if constexpr (sizeof(T) == 4) {
-        if (ev == 4) z_ev<T, 4>(N, in, out, spec, g, tw, tk, blocks, s);
-        else z_ev<T, 8>(N, in, out, spec, g, tw, tk, blocks, s);
-    } else {
-        if (ev == 2) z_ev<T, 2>(N, in, out, spec, g, tw, tk, blocks, s);
-        else z_ev<T, 4>(N, in, out, spec, g, tw, tk, blocks, s);
-    }
+    if constexpr (sizeof(T) == 4)
+        z_ev<T, 4>(N, in, out, spec, g, tw, tk, blocks, s);
+    else
+        z_ev<T, 2>(N, in, out, spec, g, tw, tk, blocks, s);
     check_hip(hipGetLastError(), "fused z launch");
 }
 

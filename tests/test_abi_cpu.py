@@ -61,3 +61,16 @@ def test_unsupported_sizes_and_flags():
 def test_padded_lengths():
     assert B.padded_lengths((32, 128, 1)) == (64, 256, 2)
     assert B.padded_lengths((5, 3, 7)) == (16, 8, 16)
+
+
+def test_footprint_predicts_mirror_compression():
+    tilt = (0.26892, 0.0, 0.96316)
+    full = B.footprint(_desc(lines=[(0, 0, 1)], flags=B.FLAG_FULL_SPECTRUM))[0]
+    both = B.footprint(_desc(lines=[(0, 0, 1)]))[0]
+    ymir = B.footprint(_desc(lines=[(0, 0, 1), tilt]))[0]
+    ymir_full = B.footprint(_desc(lines=[(0, 0, 1), tilt], flags=B.FLAG_FULL_SPECTRUM))[0]
+    # grid 8 x 8 x 4 -> Py = 16, Pz = 8: kept rows 9 of 16 and 5 of 8
+    assert both < full and ymir < ymir_full
+    spec_full = full - 2048 * 8            # minus the FP32 twiddle table
+    spec_both = both - 2048 * 8
+    assert spec_both * 16 * 8 == spec_full * 9 * 5

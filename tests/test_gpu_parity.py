@@ -170,3 +170,30 @@ def test_poly_sweep_batch64_golden():
         comp, whole = rel_l2(sel, ref)
         _say(f"[{name}] per component {np.array2string(comp, precision=2)} whole {whole:.2e}")
         assert np.all(comp <= TOL[32]) and whole <= TOL[32]
+
+
+@pytest.mark.parametrize("lines,mir", [([(0.0, 0.0, 1.0)], (1, 1)), ([(0.0, 0.0, 1.0), TILT], (1, 0)),
+                                       ([DIAG], (0, 0)), ([(1.0, 0.0, 0.0), (0.0, 1.0, 0.0)], (1, 1))])
+def test_mirror_compressed_spectrum_matches_full(lines, mir):
+    """The spectrum kept for ky <= Py/2 (kz <= Pz/2) with per-plane signs gives
+    the stress of the full spectrum; the layout follows the line directions."""
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w = W.random_field((20, 14, 10), seed=17, d=(1.0, 1.0, 2.0), lines=lines)
+    outs = []
+    for flags in (0, B.FLAG_FULL_SPECTRUM):
+        desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=64, flags=flags)
+        plan = B.Plan(desc)
+        info = plan.info()
+        want = mir if flags == 0 else (0, 0)
+        assert (info.mirror_y, info.mirror_z) == want
+        rho = torch.from_numpy(w["rho"]).to("cuda")
+        plan.set_density(rho)
+        out = plan.new_output()
+        plan.stress(out)
+        torch.cuda.synchronize()
+        outs.append((out.cpu().numpy(), info.cached_bytes))
+        plan.close()
+    (a, ca), (b, cb) = outs
+    assert np.linalg.norm(a - b) <= 1e-14 * np.linalg.norm(b)
+    assert ca <= cb
