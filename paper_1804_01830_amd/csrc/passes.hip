@@ -22,7 +22,7 @@ template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
                                                int64_t nrows, int n_in, int64_t in_stride,
                                                int64_t out_stride, const cplx<T>* __restrict__ tw,
-                                               int rows_per_block) {
+                                               int rows_per_block, int pairs) {
     constexpr int Tc = M / E;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -33,13 +33,22 @@ __global__ void __launch_bounds__(512) k_x_r2c(const T* __restrict__ in, cplx<T>
     const RowMajor lay{M + 1};
     const T* src = in + (valid ? row : 0) * in_stride;
     cplx<T> reg[E];
+    if (pairs) {        // rows aligned to a pair of reals and n_in even: one access per pair
+        const cplx<T>* src2 = reinterpret_cast<const cplx<T>*>(src);
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int i0 = 2 * (j + Tc * m);
-        T a = T(0), b = T(0);
-        if (valid && i0 < n_in) a = src[i0];
-        if (valid && i0 + 1 < n_in) b = src[i0 + 1];
-        reg[m] = {a, b};
+        for (int m = 0; m < E; ++m) {
+            const int p = j + Tc * m;
+            reg[m] = (valid && 2 * p < n_in) ? src2[p] : cplx<T>{T(0), T(0)};
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int i0 = 2 * (j + Tc * m);
+            T a = T(0), b = T(0);
+            if (valid && i0 < n_in) a = src[i0];
+            if (valid && i0 + 1 < n_in) b = src[i0 + 1];
+            reg[m] = {a, b};
+        }
     }
     fft_regs<T, M, E, true>(reg, lds, lay, rl, j, tw + (M - 1));
     __syncthreads();
@@ -75,7 +84,7 @@ template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
                                                int64_t nrows, int n_out, int64_t in_stride,
                                                int64_t out_stride, const cplx<T>* __restrict__ tw,
-                                               int rows_per_block) {
+                                               int rows_per_block, int pairs) {
     constexpr int Tc = M / E;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -106,11 +115,20 @@ __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T
     fft_regs<T, M, E, false>(reg, lds, lay, rl, j, tw + (M - 1));
     if (!valid) return;
     T* dst = out + row * out_stride;
+    if (pairs) {        // rows aligned to a pair of reals and n_out even
+        cplx<T>* dst2 = reinterpret_cast<cplx<T>*>(dst);
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int i0 = 2 * (j + Tc * m);
-        if (i0 < n_out) dst[i0] = reg[m].x;
-        if (i0 + 1 < n_out) dst[i0 + 1] = reg[m].y;
+        for (int m = 0; m < E; ++m) {
+            const int p = j + Tc * m;
+            if (2 * p < n_out) dst2[p] = reg[m];
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int i0 = 2 * (j + Tc * m);
+            if (i0 < n_out) dst[i0] = reg[m].x;
+            if (i0 + 1 < n_out) dst[i0 + 1] = reg[m].y;
+        }
     }
 }
 
@@ -167,7 +185,7 @@ __global__ void __launch_bounds__(512) k_col_fft(const cplx<T>* in, cplx<T>* out
 // requested before the current transform, whose barriers do not wait for
 // global loads, so their latency overlaps the FFT work.
 // ----------------------------------------------------------------------------
-template <typename T, int N, int E>
+template <typename T, int N, int E, int NC>
 __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
                                                  const T* __restrict__ spec, ZGeom g,
                                                  const cplx<T>* __restrict__ tw, int tk) {
@@ -212,15 +230,11 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
 #define DDS_LOAD_SPEC(DST, CH)                                                             \
     {                                                                                      \
         _Pragma("unroll") for (int v = 0; v < 6; ++v) {                                    \
-            const int bit_ = (CH) * 6 + v;                                                 \
-            const T sy_ = (flip_y && ((g.sgn_y >> bit_) & 1)) ? T(-1) : T(1);              \
-            const T sz_ = ((g.sgn_z >> bit_) & 1) ? -sy_ : sy_;                            \
-            const int base_ = bit_ * nkz;                                                  \
+            const int base_ = ((CH) * 6 + v) * nkz;                                        \
             _Pragma("unroll") for (int m = 0; m < E; ++m) {                                \
-                if (!zc || 2 * m < E)                                                      \
-                    DST[v][m] = sy_ * buf_real<T>(srs, s_lane, (base_ + Tc * m) * tk * (int)sizeof(T)); \
-                else                                                                       \
-                    DST[v][m] = sz_ * buf_real<T>(srs, s_lane_m, (base_ + Tc * (E - 1 - m)) * tk * (int)sizeof(T)); \
+                const bool mir_ = zc && (2 * m >= E);      /* uniform: selects, no branch */ \
+                DST[v][m] = buf_real<T>(srs, mir_ ? s_lane_m : s_lane,                     \
+                                        (base_ + (mir_ ? Tc * (E - 1 - m) : Tc * m)) * tk * (int)sizeof(T)); \
             }                                                                              \
         }                                                                                  \
     }
@@ -235,21 +249,33 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
         for (int v = 0; v < 6; ++v)
 #pragma unroll
             for (int m = 0; m < E; ++m) acc[v][m] = {T(0), T(0)};
-        for (int ch = 0; ch < g.C; ++ch) {
-            const bool more = ch + 1 < g.C;
-            if (more) DDS_LOAD_RHO(nxt, b, ch + 1)
-            fft_regs<T, N, E, true>(cur, lds, lay, c, j, twN);
+        // channels in groups of three (one line direction): unrolled inside a
+        // group, a runtime loop over the groups
+        for (int l = 0; l < NC / 3; ++l) {
 #pragma unroll
-            for (int v = 0; v < 6; ++v)
+            for (int gq = 0; gq < 3; ++gq) {
+                const int ch = 3 * l + gq;
+                const bool more = gq < 2 || l + 1 < NC / 3;
+                if (more) DDS_LOAD_RHO(nxt, b, ch + 1)
+                fft_regs<T, N, E, true>(cur, lds, lay, c, j, twN);
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    acc[v][m].x -= sv[v][m] * cur[m].y;
-                    acc[v][m].y += sv[v][m] * cur[m].x;
+                for (int v = 0; v < 6; ++v) {
+                    // signs of mirrored spectrum rows (wave-uniform)
+                    const int bit = ch * 6 + v;
+                    const T sy = (flip_y && ((g.sgn_y >> bit) & 1)) ? T(-1) : T(1);
+                    const T sz = ((g.sgn_z >> bit) & 1) ? -sy : sy;
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const T sval = ((zc && 2 * m >= E) ? sz : sy) * sv[v][m];
+                        acc[v][m].x -= sval * cur[m].y;
+                        acc[v][m].y += sval * cur[m].x;
+                    }
                 }
-            if (more) {
-                DDS_LOAD_SPEC(sv, ch + 1)
+                if (more) {
+                    DDS_LOAD_SPEC(sv, ch + 1)
 #pragma unroll
-                for (int m = 0; m < E; ++m) cur[m] = nxt[m];
+                    for (int m = 0; m < E; ++m) cur[m] = nxt[m];
+                }
             }
         }
         if (b + 1 < g.B) {      // first channel of the next realisation
@@ -321,17 +347,24 @@ int default_z_tk(int N, int elem_bytes) {
 #define DDS_FOR_LENGTHS(X, EV) X(1, EV) X(2, EV) X(4, EV) X(8, EV) X(16, EV) X(32, EV) X(64, EV) \
     X(128, EV) X(256, EV) X(512, EV) X(1024, EV)
 
+// Real rows can be accessed in pairs when every row starts on a pair boundary.
+template <typename T>
+static int pairs_ok(const T* base, int64_t stride, int n) {
+    return ((reinterpret_cast<uintptr_t>(base) % (2 * sizeof(T))) == 0 && stride % 2 == 0 && n % 2 == 0) ? 1 : 0;
+}
+
 template <typename T, int EV>
 static void x_r2c_ev(int M, const T* in, cplx<T>* out, int64_t nrows, int n_in, int64_t in_stride,
                      int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
     const int64_t blocks = (nrows + rows - 1) / rows;
+    const int pairs = pairs_ok(in, in_stride, n_in);
     const size_t lds = (size_t)rows * (M + 1) * sizeof(cplx<T>);
     switch (M) {
 #define X_CASE(L, EVV)                                                                                     \
     case L: {                                                                                              \
         constexpr int E = L < EVV ? L : EVV;                                                               \
         hipLaunchKernelGGL((k_x_r2c<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, in, out, \
-                           nrows, n_in, in_stride, out_stride, tw, rows);                                  \
+                           nrows, n_in, in_stride, out_stride, tw, rows, pairs);                           \
         break;                                                                                             \
     }
         DDS_FOR_LENGTHS(X_CASE, EV)
@@ -344,13 +377,14 @@ template <typename T, int EV>
 static void x_c2r_ev(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
                      int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
     const int64_t blocks = (nrows + rows - 1) / rows;
+    const int pairs = pairs_ok(out, out_stride, n_out);
     const size_t lds = (size_t)rows * (M + 1) * sizeof(cplx<T>);
     switch (M) {
 #define X_CASE(L, EVV)                                                                                     \
     case L: {                                                                                              \
         constexpr int E = L < EVV ? L : EVV;                                                               \
         hipLaunchKernelGGL((k_x_c2r<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, in, out, \
-                           nrows, n_out, in_stride, out_stride, tw, rows);                                 \
+                           nrows, n_out, in_stride, out_stride, tw, rows, pairs);                          \
         break;                                                                                             \
     }
         DDS_FOR_LENGTHS(X_CASE, EV)
@@ -377,7 +411,7 @@ static void col_ev(int N, const cplx<T>* in, cplx<T>* out, const ColGeom& g, con
     }
 }
 
-template <typename T, int EV>
+template <typename T, int EV, int NC>
 static void z_ev(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g, const cplx<T>* tw,
                  int tk, int64_t blocks, hipStream_t s) {
     const size_t lds = (size_t)N * tk * sizeof(cplx<T>);
@@ -385,8 +419,8 @@ static void z_ev(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZG
 #define Z_CASE(L, EVV)                                                                                     \
     case L: {                                                                                              \
         constexpr int E = L < EVV ? L : EVV;                                                               \
-        hipLaunchKernelGGL((k_z_fused<T, L, E>), dim3((unsigned)blocks), dim3(tk * (L / E)), lds, s, in, out, \
-                           spec, g, tw, tk);                                                               \
+        hipLaunchKernelGGL((k_z_fused<T, L, E, NC>), dim3((unsigned)blocks), dim3(tk * (L / E)), lds, s, in, \
+                           out, spec, g, tw, tk);                                                          \
         break;                                                                                             \
     }
         DDS_FOR_LENGTHS(Z_CASE, EV)
@@ -436,10 +470,13 @@ void launch_z_fused(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spe
     const int64_t blocks = (int64_t)g.ntiles * g.nky;
     if (blocks <= 0) return;
     if (!ev_z_ok(ev, (int)sizeof(T))) fail(DDSTRESS_E_INVALID, "z element class not supported for this precision");
-    if constexpr (sizeof(T) == 4)
-        z_ev<T, 4>(N, in, out, spec, g, tw, tk, blocks, s);
-    else
-        z_ev<T, 2>(N, in, out, spec, g, tw, tk, blocks, s);
+    constexpr int EV = sizeof(T) == 4 ? 4 : 2;
+    switch (g.C) {     // the channel loop is unrolled: one instance per line count
+        case 3: z_ev<T, EV, 3>(N, in, out, spec, g, tw, tk, blocks, s); break;
+        case 6: z_ev<T, EV, 6>(N, in, out, spec, g, tw, tk, blocks, s); break;
+        case 9: z_ev<T, EV, 9>(N, in, out, spec, g, tw, tk, blocks, s); break;
+        default: fail(DDSTRESS_E_INVALID, "channel count must be 3, 6 or 9");
+    }
     check_hip(hipGetLastError(), "fused z launch");
 }
 
