@@ -102,6 +102,7 @@ typedef struct {
     int32_t tile_y;        /* columns per block of the y passes */
     int32_t rows_x;        /* rows per block of the x passes */
     int32_t ex, ey, ez;    /* element classes of the x, y and fused z passes (see ddstress_tuning) */
+    int32_t z_groups;      /* thread groups per column tile of the fused z pass (see ddstress_tuning) */
     int32_t mirror_y;      /* 1: every coefficient plane is even or odd under y -> -y (each line direction
                               has t_y = 0 or is parallel to e_y), so the spectrum is kept for ky <= Py/2
                               only, with a sign per plane for the mirrored rows */
@@ -115,7 +116,11 @@ typedef struct {
 /* Launch shapes of the passes: a tuning choice. A transform of length N runs
  * with E = min(N, e) elements per thread and radices <= E, where the element
  * class e is 8 or 16 for the x and y passes and 4 (FP32) / 2 (FP64) for the
- * fused z pass; 0 selects the default. Tile sizes change which
+ * fused z pass (for Pz >= 256 also 2, 4 or 8 times that, at most 16); 0
+ * selects the default. The fused z pass runs either one thread group per
+ * column tile, which transforms every channel and stress component, or one
+ * group per density channel (z_groups = C), which split the transforms; both
+ * sum the channels in the same order. Tile sizes and group counts change which
  * threads do the work, not the arithmetic (bit-identical results); element
  * classes change the radix sequence and hence the rounding (within the
  * stated tolerances). */
@@ -124,6 +129,7 @@ typedef struct {
     int32_t tk_y;          /* consecutive kx columns per block of the y passes */
     int32_t tk_z;          /* consecutive kx columns per block of the fused z pass */
     int32_t ex, ey, ez;    /* element classes of the x, y and fused z passes (0: default) */
+    int32_t z_groups;      /* fused z thread groups: 1 or C (0: default, C when batch >= 16) */
     float   ms[3];         /* autotune: median device ms of the chosen x pair, y pair and z pass */
 } ddstress_tuning;
 
@@ -145,8 +151,9 @@ ddstress_status ddstress_plan_footprint(const ddstress_desc* desc, size_t* cache
  * device memory until ddstress_plan_destroy. */
 ddstress_status ddstress_plan_create(const ddstress_desc* desc, void* stream, ddstress_plan* out);
 
-/* Autotuner: times every admissible tile size and element class of each pass
- * (threads per block <= 512, LDS <= 64 KiB) on zero-filled buffers of the descriptor's
+/* Autotuner: times every admissible tile size, element class and z group
+ * count of each pass (threads per block <= 512, 768 for the grouped z pass;
+ * LDS <= 64 KiB) on zero-filled buffers of the descriptor's
  * shape, precision and batch, with HIP events on `stream` (median of five runs
  * after two warm-up runs), and returns the fastest per pass. Synchronous;
  * allocates its buffers for the duration of the call. */

@@ -84,6 +84,7 @@ struct Shape {
     int C, B, L;
     int elem;        // bytes per real
     int tkz, ntz;    // fused z tile and number of kx tiles
+    int zg;          // fused z thread groups: 1, or one per channel (C)
     bool mir_y, mir_z;          // spectrum kept for ky <= Py/2 (kz <= Pz/2) only, by mirror parity
     int nkys, nkzs;             // spectrum rows kept along ky and kz
     uint64_t sgn_y, sgn_z;      // bit c*6+v: S_{v,c} odd under ky -> -ky (kz -> -kz)
@@ -147,7 +148,8 @@ Shape make_shape(const ddstress_desc* d) {
     s.C = 3 * d->n_lines;
     s.B = d->batch;
     s.elem = d->precision == 32 ? 4 : 8;
-    s.tkz = default_z_tk(s.P[2], s.elem);
+    s.zg = default_z_groups(s.C, s.B);
+    s.tkz = default_z_tk(s.P[2], s.C, s.zg, s.elem);
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
     set_mirrors(s, predict_mirror(d, 1), predict_mirror(d, 2));
     s.sgn_y = s.sgn_z = 0;
@@ -406,7 +408,7 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     gz.ors = gz.irs;
     gz.oqs = gz.iqs;
     gz.oos = gz.ios;
-    launch_z_fused<T>(s.P[2], p->ez, w2, w1, p->spec->as<T>(), gz, tw, s.tkz, st);
+    launch_z_fused<T>(s.P[2], p->ez, s.zg, w2, w1, p->spec->as<T>(), gz, tw, s.tkz, st);
     p->mark(st);
     // y inverse: Py rows -> Ny rows
     ColGeom gi{};
@@ -475,35 +477,40 @@ void enqueue_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStrea
 constexpr int kMaxThreads = 512;
 constexpr size_t kMaxLds = 64 * 1024;
 bool rows_ok(const Shape& s, int r, int ev) {
+    const int e = s.M < ev ? s.M : ev;
     return r >= 1 && ev_col_ok(ev) && x_threads(s.M, r, ev) <= kMaxThreads &&
-           (size_t)r * (s.M + 1) * 2 * s.elem <= kMaxLds;
+           (size_t)r * x_lds_ld(s.M, e, s.elem) * 2 * s.elem <= kMaxLds;
 }
 bool col_ok(const Shape& s, int N, int tk, int ev) {
     return tk >= 1 && ev_col_ok(ev) && col_threads(N, tk, ev) <= kMaxThreads &&
            (size_t)N * tk * 2 * s.elem <= kMaxLds;
 }
-bool z_ok(const Shape& s, int tk, int ev) {
-    return tk >= 1 && ev_z_ok(ev, s.elem) && z_threads(s.P[2], tk, ev) <= kMaxThreads &&
-           (size_t)s.P[2] * tk * 2 * s.elem <= kMaxLds;
+bool z_ok(const Shape& s, int tk, int ev, int groups) {
+    return tk >= 1 && z_groups_ok(groups, s.C) && ev_z_ok(s.P[2], ev, s.elem) &&
+           z_threads(s.P[2], groups, tk, ev) <= z_max_threads(groups) &&
+           z_lds_bytes(s.P[2], tk, s.C, groups, s.elem) <= kMaxLds;
 }
 
 struct LaunchChoice {
-    int rows_x, ex, tk_y, ey, ez;
+    int rows_x, ex, tk_y, ey, ez, zg;
 };
 
 LaunchChoice default_launch(const Shape& s) {
     return {default_rows(s.M, s.elem), default_ev_col(s.M), default_col_tk(s.P[1], s.elem), default_ev_col(s.P[1]),
-            default_ev_z(s.elem)};
+            default_ev_z(s.P[2], s.zg, s.elem), s.zg};
 }
 
 // Apply a tuning (zero element classes select the defaults) after checking it.
 LaunchChoice apply_tuning(Shape& s, const ddstress_tuning* t) {
     LaunchChoice c = default_launch(s);
     if (!t) return c;
-    const int ex = t->ex ? t->ex : c.ex, ey = t->ey ? t->ey : c.ey, ez = t->ez ? t->ez : c.ez;
-    if (!rows_ok(s, t->rows_x, ex) || !col_ok(s, s.P[1], t->tk_y, ey) || !z_ok(s, t->tk_z, ez))
+    const int zg = t->z_groups ? t->z_groups : c.zg;
+    const int ex = t->ex ? t->ex : c.ex, ey = t->ey ? t->ey : c.ey;
+    const int ez = t->ez ? t->ez : default_ev_z(s.P[2], zg, s.elem);
+    if (!rows_ok(s, t->rows_x, ex) || !col_ok(s, s.P[1], t->tk_y, ey) || !z_ok(s, t->tk_z, ez, zg))
         fail(DDSTRESS_E_INVALID, "tuning choice outside the launch limits of this shape");
-    c = {t->rows_x, ex, t->tk_y, ey, ez};
+    c = {t->rows_x, ex, t->tk_y, ey, ez, zg};
+    s.zg = zg;
     s.tkz = t->tk_z;
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
     return c;
@@ -579,17 +586,21 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
     Shape s = make_shape(desc);
     const int64_t BC = (int64_t)s.B * s.C, B6 = (int64_t)s.B * 6;
     const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2], Py = s.P[1], Pz = s.P[2];
-    const std::vector<int> zev = {default_ev_z(s.elem)};
-    std::vector<std::pair<int, int>> zlist;     // (tk, ev)
-    for (int ev : zev)
-        for (int tk = 1; tk <= 256; tk *= 2)
-            if (z_ok(s, tk, ev) && z_threads(Pz, tk, ev) >= 64) zlist.push_back({tk, ev});
-    if (zlist.empty()) zlist.push_back({s.tkz, default_ev_z(s.elem)});
+    std::vector<int> zev;
+    for (int ev = 2; ev <= 16; ev *= 2)
+        if (ev_z_ok(Pz, ev, s.elem)) zev.push_back(ev);
+    struct ZChoice { int tk, ev, groups; };
+    std::vector<ZChoice> zlist;
+    for (int groups : {1, s.C})
+        for (int ev : zev)
+            for (int tk = 1; tk <= 256; tk *= 2)
+                if (z_ok(s, tk, ev, groups) && z_threads(Pz, groups, tk, ev) >= 64) zlist.push_back({tk, ev, groups});
+    if (zlist.empty()) zlist.push_back({s.tkz, default_ev_z(Pz, s.zg, s.elem), s.zg});
     size_t spec_max = 0;
     for (auto& z : zlist) {
         Shape t = s;
-        t.tkz = z.first;
-        t.ntz = (s.M1 + z.first - 1) / z.first;
+        t.tkz = z.tk;
+        t.ntz = (s.M1 + z.tk - 1) / z.tk;
         spec_max = std::max(spec_max, spec_bytes(t));
     }
     DevBuf rho, sig, w1, w2, spec, tw;
@@ -641,17 +652,23 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
         }
     best = 1e30f;
     for (auto& z : zlist) {
-        const int tk = z.first, ev = z.second;
+        const int tk = z.tk, ev = z.ev, groups = z.groups;
         ZGeom gz{};
         gz.nky_s = s.nkys; gz.nkz_s = s.nkzs;
         gz.ncols = s.M1; gz.ntiles = (s.M1 + tk - 1) / tk; gz.nky = Py; gz.nz = Nz; gz.C = s.C; gz.B = s.B;
         gz.irs = (int64_t)Py * s.wx; gz.iqs = (int64_t)Nz * Py * s.wx; gz.ios = s.wx;
         gz.ors = gz.irs; gz.oqs = gz.iqs; gz.oos = gz.ios;
         float ms = time_median(st, reps, [&] {
-            launch_z_fused<T>(Pz, ev, w2.as<cplx<T>>(), w1.as<cplx<T>>(), spec.as<T>(), gz, twp, tk, st);
+            launch_z_fused<T>(Pz, ev, groups, w2.as<cplx<T>>(), w1.as<cplx<T>>(), spec.as<T>(), gz, twp, tk, st);
         });
-        if (verbose) std::fprintf(stderr, "[tune] z tk=%d ev=%d %.5f ms\n", tk, ev, ms);
-        if (ms < best) { best = ms; out->tk_z = tk; out->ez = ev; out->ms[2] = ms; }
+        if (verbose) std::fprintf(stderr, "[tune] z tk=%d ev=%d groups=%d %.5f ms\n", tk, ev, groups, ms);
+        if (ms < best) {
+            best = ms;
+            out->tk_z = tk;
+            out->ez = ev;
+            out->z_groups = groups;
+            out->ms[2] = ms;
+        }
     }
     check_hip(hipStreamSynchronize(st), "tuning");
 }
@@ -754,6 +771,7 @@ ddstress_status ddstress_plan_share(ddstress_plan src, int32_t batch, ddstress_p
             p->shape = make_shape(&p->desc);
             p->shape.tkz = src->shape.tkz;      // the shared spectrum's layout
             p->shape.ntz = src->shape.ntz;
+            p->shape.zg = src->shape.zg;
             p->shape.mir_y = src->shape.mir_y;
             p->shape.mir_z = src->shape.mir_z;
             p->shape.nkys = src->shape.nkys;
@@ -815,6 +833,7 @@ ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info) 
         info->ex = plan->ex;
         info->ey = plan->ey;
         info->ez = plan->ez;
+        info->z_groups = s.zg;
         info->cached_bytes = plan->spec->bytes + plan->tw->bytes;
         info->work_bytes = plan->work1.bytes + plan->work2.bytes + plan->rho_own.bytes + plan->sigma_tmp.bytes;
         info->kernel_real_max = plan->re_max;

@@ -73,20 +73,26 @@ struct ZGeom {
     int64_t ors, oqs, oos; // output strides (6B planes)
 };
 template <typename T>
-void launch_z_fused(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+void launch_z_fused(int N, int ev, int groups, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
                     const cplx<T>* tw, int tk, hipStream_t s);
 
 // Launch geometry: threads per block, element classes and defaults.
 int x_threads(int M, int rows, int ev);
+int x_lds_ld(int M, int E, int elem_bytes);
 int col_threads(int N, int tk, int ev);
-int z_threads(int N, int tk, int ev);
+int z_threads(int N, int groups, int tk, int ev);
 int default_ev_col(int N);
-int default_ev_z(int elem_bytes);
+int default_ev_z(int N, int groups, int elem_bytes);
 bool ev_col_ok(int ev);
-bool ev_z_ok(int ev, int elem_bytes);
+bool ev_z_ok(int N, int ev, int elem_bytes);
 int default_col_tk(int N, int elem_bytes);
 int default_rows(int M, int elem_bytes);
-int default_z_tk(int N, int elem_bytes);
+int default_z_tk(int N, int C, int groups, int elem_bytes);
+size_t z_lds_bytes(int N, int tk, int C, int groups, int elem_bytes);
+int z_lds_ld(int tk, int elem_bytes);
+bool z_groups_ok(int groups, int C);
+int default_z_groups(int C, int B);
+int z_max_threads(int groups);
 
 // ---- kernel build (kernel_build.hip) ---------------------------------------
 struct KernelParams {

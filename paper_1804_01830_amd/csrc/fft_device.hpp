@@ -98,6 +98,53 @@ __device__ __forceinline__ void dftR(cplx<T>* v) {
     else if constexpr (R == 8) dft8<FWD>(v);
 }
 
+// Length-R DFTs whose upper inputs v[R/2 .. R-1] are zero (the first stage of
+// a transform of zero-padded data); those inputs are never read. Same values
+// as the full DFTs above with zeros there.
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft4_hz(cplx<T>* v) {
+    const cplx<T> a = v[0];
+    const cplx<T> b = rot90<FWD>(v[1]);
+    v[2] = csub(a, v[1]);
+    v[0] = cadd(a, v[1]);
+    v[1] = cadd(a, b);
+    v[3] = csub(a, b);
+}
+
+template <bool FWD, typename T>
+__device__ __forceinline__ void dft8_hz(cplx<T>* v) {
+    cplx<T> e[4] = {v[0], v[2], v[0], v[0]};
+    cplx<T> o[4] = {v[1], v[3], v[1], v[1]};
+    dft4_hz<FWD>(e);
+    dft4_hz<FWD>(o);
+    const T h = T(0.70710678118654752440084436210484904);
+    cplx<T> o1, o3;
+    if (FWD) {
+        o1 = {(o[1].x + o[1].y) * h, (o[1].y - o[1].x) * h};
+        o3 = {(o[3].y - o[3].x) * h, -(o[3].x + o[3].y) * h};
+    } else {
+        o1 = {(o[1].x - o[1].y) * h, (o[1].x + o[1].y) * h};
+        o3 = {-(o[3].x + o[3].y) * h, (o[3].x - o[3].y) * h};
+    }
+    cplx<T> o2 = rot90<FWD>(o[2]);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
+template <int R, bool FWD, typename T>
+__device__ __forceinline__ void dftR_hz(cplx<T>* v) {
+    if constexpr (R == 1) {
+    } else if constexpr (R == 2) v[1] = v[0];
+    else if constexpr (R == 4) dft4_hz<FWD>(v);
+    else if constexpr (R == 8) dft8_hz<FWD>(v);
+}
+
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
 // Raw buffer loads: a 128-bit resource (base, byte size) kept in scalar
@@ -209,6 +256,178 @@ __device__ __forceinline__ void fft_stages(cplx<T> (&reg)[E], cplx<T>* lds, Lay 
         fft_stage<T, N, E, FWD, Ns, R>(reg, lds, lay, c, j, tw);
         fft_stages<T, N, E, FWD, Ns * R>(reg, lds, lay, c, j, tw);
     }
+}
+
+// Twiddles of every stage after the first, for the butterflies one thread
+// owns: count, load (once) and a stage that takes them from registers. A
+// kernel that runs many transforms of one length keeps them for all of them
+// (the inverse uses their conjugates).
+constexpr int tw_count(int N, int E, int Ns = 1) {
+    return Ns >= N ? 0
+                   : (Ns == 1 ? 0 : (E / cmin(cmin(8, E), N / Ns)) * (cmin(cmin(8, E), N / Ns) - 1)) +
+                         tw_count(N, E, Ns * cmin(cmin(8, E), N / Ns));
+}
+
+template <typename T, int N, int E, int Ns, int K, int TWC>
+__device__ __forceinline__ void load_tw_stages(cplx<T> (&w)[TWC], int j, const cplx<T>* __restrict__ tw) {
+    if constexpr (Ns < N) {
+        constexpr int R = cmin(cmin(8, E), N / Ns);
+        constexpr int Tc = N / E;
+        constexpr int NB = E / R;
+        if constexpr (Ns > 1) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int k = (j + Tc * q) & (Ns - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[K + q * (R - 1) + r - 1] = tw[k * r * (N / (Ns * R))];
+            }
+            load_tw_stages<T, N, E, Ns * R, K + NB * (R - 1)>(w, j, tw);
+        } else {
+            load_tw_stages<T, N, E, Ns * R, K>(w, j, tw);
+        }
+    }
+}
+
+template <typename T, int N, int E, bool FWD, int Ns, int R, int K, int TWC, class Lay>
+__device__ __forceinline__ void fft_stage_tw(cplx<T> (&reg)[E], const cplx<T> (&w)[TWC], cplx<T>* lds, Lay lay,
+                                             int c, int j) {
+    constexpr int Tc = N / E;
+    constexpr int NB = E / R;
+    constexpr bool first = (Ns == 1);
+    constexpr bool last = (Ns * R == N);
+    cplx<T> v[NB][R];
+    if constexpr (first) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = reg[q + r * NB];
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = lds[lay(j + Tc * q + r * (N / R), c)];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        if constexpr (!first) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[q][r] = twmul<FWD>(v[q][r], w[K + q * (R - 1) + r - 1]);
+        }
+        dftR<R, FWD>(v[q]);
+    }
+    if constexpr (last) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+#pragma unroll
+            for (int r = 0; r < R; ++r) reg[q + r * NB] = v[q][r];
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int b = j + Tc * q;
+            const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
+#pragma unroll
+            for (int r = 0; r < R; ++r) lds[lay(base + r * Ns, c)] = v[q][r];
+        }
+    }
+}
+
+template <typename T, int N, int E, bool FWD, int Ns, int K, int TWC, class Lay>
+__device__ __forceinline__ void fft_stages_tw(cplx<T> (&reg)[E], const cplx<T> (&w)[TWC], cplx<T>* lds, Lay lay,
+                                              int c, int j) {
+    if constexpr (Ns < N) {
+        constexpr int R = cmin(cmin(8, E), N / Ns);
+        fft_stage_tw<T, N, E, FWD, Ns, R, K, TWC>(reg, w, lds, lay, c, j);
+        fft_stages_tw<T, N, E, FWD, Ns * R, (Ns == 1 ? K : K + (E / R) * (R - 1)), TWC>(reg, w, lds, lay, c, j);
+    }
+}
+
+// Transform with the twiddles already in registers (see load_tw_stages).
+template <typename T, int N, int E, bool FWD, int TWC, class Lay>
+__device__ __forceinline__ void fft_regs_tw(cplx<T> (&reg)[E], const cplx<T> (&w)[TWC], cplx<T>* lds, Lay lay, int c,
+                                            int j) {
+    static_assert(N % E == 0, "E must divide N");
+    fft_stages_tw<T, N, E, FWD, 1, 0, TWC>(reg, w, lds, lay, c, j);
+}
+
+// K transforms of length N taken through the stages together, with the
+// twiddles in registers (see load_tw_stages): one barrier before the reads and
+// one before the writes of each stage serve all K, whose exchanges use the LDS
+// regions lds + k * region. HZ: inputs m >= E/2 of every transform are zero
+// (zero-padded data) and are not read.
+template <typename T, int N, int E, bool FWD, bool HZ, int Ns, int R, int KT, int K, int TWC, class Lay>
+__device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
+                                           Lay lay, int c, int j) {
+    constexpr int Tc = N / E;
+    constexpr int NB = E / R;
+    constexpr bool first = (Ns == 1);
+    constexpr bool last = (Ns * R == N);
+    cplx<T> v[K][NB][R];
+    if constexpr (first) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int r = 0; r < (HZ ? (R + 1) / 2 : R); ++r) v[k][q][r] = reg[k][q + r * NB];
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[k][q][r] = lds[k * region + lay(j + Tc * q + r * (N / R), c)];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            if constexpr (!first) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[k][q][r] = twmul<FWD>(v[k][q][r], w[KT + q * (R - 1) + r - 1]);
+            }
+            if constexpr (first && HZ) dftR_hz<R, FWD>(v[k][q]);
+            else dftR<R, FWD>(v[k][q]);
+        }
+    if constexpr (last) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < NB; ++q)
+#pragma unroll
+                for (int r = 0; r < R; ++r) reg[k][q + r * NB] = v[k][q][r];
+    } else {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int b = j + Tc * q;
+                const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[k * region + lay(base + r * Ns, c)] = v[k][q][r];
+            }
+    }
+}
+
+template <typename T, int N, int E, bool FWD, bool HZ, int Ns, int KT, int K, int TWC, class Lay>
+__device__ __forceinline__ void fftk_stages(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
+                                            Lay lay, int c, int j) {
+    if constexpr (Ns < N) {
+        constexpr int R = cmin(cmin(8, E), N / Ns);
+        fftk_stage<T, N, E, FWD, HZ, Ns, R, KT, K, TWC>(reg, w, lds, region, lay, c, j);
+        fftk_stages<T, N, E, FWD, HZ, Ns * R, (Ns == 1 ? KT : KT + (E / R) * (R - 1)), K, TWC>(reg, w, lds, region,
+                                                                                              lay, c, j);
+    }
+}
+
+template <typename T, int N, int E, bool FWD, bool HZ, int K, int TWC, class Lay>
+__device__ __forceinline__ void fft_regs_k(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
+                                           Lay lay, int c, int j) {
+    static_assert(N % E == 0, "E must divide N");
+    fftk_stages<T, N, E, FWD, HZ, 1, 0, K, TWC>(reg, w, lds, region, lay, c, j);
 }
 
 // Full transform of length N on the register distribution described above.

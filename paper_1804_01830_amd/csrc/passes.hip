@@ -12,6 +12,17 @@
 
 namespace dds {
 
+// The hardware hands consecutive workgroups of a launch to the eight XCDs in
+// turn, and each XCD has its own L2. Logical block index of workgroup b of nb
+// such that every XCD works through one contiguous range of logical blocks
+// (neighbouring column tiles, which share cache lines, then meet in one L2).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int x = b % X, i = b / X;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 // ----------------------------------------------------------------------------
 // x: real-to-complex of length P = 2M. Row r has n_in reals (the rest of the P
 // inputs are zero). The reals are packed in pairs, z[m] = x[2m] + i x[2m+1],
@@ -22,7 +33,7 @@ template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
                                                int64_t nrows, int n_in, int64_t in_stride,
                                                int64_t out_stride, const cplx<T>* __restrict__ tw,
-                                               int rows_per_block, int pairs) {
+                                               int rows_per_block, int pairs, int ld) {
     constexpr int Tc = M / E;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -30,7 +41,7 @@ __global__ void __launch_bounds__(512) k_x_r2c(const T* __restrict__ in, cplx<T>
     const int rl = threadIdx.x / Tc;
     const int64_t row = (int64_t)blockIdx.x * rows_per_block + rl;
     const bool valid = row < nrows;
-    const RowMajor lay{M + 1};
+    const RowMajor lay{ld};
     const T* src = in + (valid ? row : 0) * in_stride;
     cplx<T> reg[E];
     if (pairs) {        // rows aligned to a pair of reals and n_in even: one access per pair
@@ -84,7 +95,7 @@ template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
                                                int64_t nrows, int n_out, int64_t in_stride,
                                                int64_t out_stride, const cplx<T>* __restrict__ tw,
-                                               int rows_per_block, int pairs) {
+                                               int rows_per_block, int pairs, int ld) {
     constexpr int Tc = M / E;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -92,7 +103,7 @@ __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T
     const int rl = threadIdx.x / Tc;
     const int64_t row = (int64_t)blockIdx.x * rows_per_block + rl;
     const bool valid = row < nrows;
-    const RowMajor lay{M + 1};
+    const RowMajor lay{ld};
     const cplx<T>* src = in + (valid ? row : 0) * in_stride;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -173,38 +184,44 @@ __global__ void __launch_bounds__(512) k_col_fft(const cplx<T>* in, cplx<T>* out
 }
 
 // ----------------------------------------------------------------------------
-// Fused z pass. A block owns `tk` consecutive kx columns at one ky. For every
-// realisation b it transforms the C density columns along z (length N, nz
-// inputs), accumulates the six stress spectra
-//     sigma^_v(k) = sum_c i S_{v,c}(k) rho^_c(k)        (K^ = i S, K odd)
-// in registers with a fixed channel order, and transforms each back along z,
-// writing the first nz rows. The spectrum tile of the block is stored
-// contiguously as [c][v][kz][tk].
-// The loads are software-pipelined: the density column and the spectrum
-// values of the next channel (or of the next realisation's first channel) are
-// requested before the current transform, whose barriers do not wait for
-// global loads, so their latency overlaps the FFT work.
+// Fused z pass, single-group form. A block owns `tk` consecutive kx columns at
+// one ky and one group of Tc * tk threads. For every realisation b it
+// transforms the C density columns along z one after the other (rows
+// z >= N/2 are the zero padding and are not loaded), accumulates the six
+// stress spectra
+//     sigma^_v(k) = sum_c i S_{v,c}(k) rho^_c(k)      (K^ = i S, K odd)
+// in registers, summing the channels in increasing order (the same arithmetic
+// as the grouped form), and transforms each back along z, writing rows
+// z < nz. The density column and spectrum values of the next channel (or of
+// the next realisation's first channel) are requested before the current
+// transform, so their latency overlaps the FFT work. Fewer threads per column
+// than the grouped form: better for few realisations.
 // ----------------------------------------------------------------------------
 template <typename T, int N, int E, int NC>
-__global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-                                                 const T* __restrict__ spec, ZGeom g,
-                                                 const cplx<T>* __restrict__ tw, int tk) {
+__global__ void __launch_bounds__(512) k_z_serial(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                  const T* __restrict__ spec, ZGeom g,
+                                                  const cplx<T>* __restrict__ tw, int tk, int ld) {
     constexpr int Tc = N / E;
+    constexpr int EH = (E + 1) / 2;        // elements that can hold data rows (z < N/2)
+    constexpr bool HZ = N > 1;             // the upper half of every input column is padding
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
     const int c = threadIdx.x % tk;
     const int j = threadIdx.x / tk;
-    const int tile = blockIdx.x % g.ntiles;
-    const int ky = blockIdx.x / g.ntiles;
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int tile = blk % g.ntiles;
+    const int ky = blk / g.ntiles;
     const int col = tile * tk + c;
     const bool valid = col < g.ncols;
     const int colc = valid ? col : 0;
-    const ColMajor lay{tk};
-    const cplx<T>* twN = tw + (N - 1);
-    const int ors = (int)g.ors;                      // in-block offsets fit in 32 bits
+    const ColMajor lay{ld};
+    constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
+    cplx<T> twr[TWC];
+    load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
+    const int ors = (int)g.ors;
     // Spectrum tile of this block: [c][v][kzc][tk] at row kyc. With a y mirror
-    // only ky <= Py/2 is stored and row Py - ky stands in for ky > Py/2; with a
-    // z mirror only kz <= N/2 is stored and elements m >= E/2 (kz >= N/2) read
+    // only ky <= Py/2 is stored and row Py - ky stands in for ky > Py/2; with
+    // a z mirror only kz <= N/2 is stored and elements m >= E/2 read
     // kz' = N - kz = (Tc - j) + Tc (E - 1 - m). Odd planes change sign.
     const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
     const int kyc = flip_y ? g.nky - ky : ky;
@@ -214,10 +231,11 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
     const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * tk * sizeof(T)));
     const int s_lane = (j * tk + c) * (int)sizeof(T);
     const int s_lane_m = ((Tc - j) * tk + c) * (int)sizeof(T);
-    // density planes: rows z < nz of the block's columns; rows >= nz lie beyond the resource (read as zero)
+    // density rows z < nz of the block's columns; rows >= nz lie beyond the
+    // resource and read as zero. Lanes of padding columns (col >= ncols) read
+    // the tile's first column, which is valid.
     const cplx<T>* in_b = in + (int64_t)ky * g.ios + (int64_t)tile * tk;
     const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
-    // lanes of padding columns (col >= ncols) read the tile's first column, which is valid
     const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
     const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
     cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
@@ -225,7 +243,7 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
 #define DDS_LOAD_RHO(DST, BB, CH)                                                          \
     {                                                                                      \
         const __amdgpu_buffer_rsrc_t rr_ = make_rsrc(in_b + (int64_t)((BB) * g.C + (CH)) * g.iqs, plane_bytes); \
-        _Pragma("unroll") for (int m = 0; m < E; ++m) DST[m] = buf_cplx<T>(rr_, r_lane, m * r_step); \
+        _Pragma("unroll") for (int m = 0; m < EH; ++m) DST[0][m] = buf_cplx<T>(rr_, r_lane, m * r_step); \
     }
 #define DDS_LOAD_SPEC(DST, CH)                                                             \
     {                                                                                      \
@@ -239,16 +257,16 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
         }                                                                                  \
     }
 
-    cplx<T> cur[E], nxt[E];
+    cplx<T> cur[1][E], nxt[1][E];
     T sv[6][E];
     DDS_LOAD_RHO(cur, 0, 0)
     DDS_LOAD_SPEC(sv, 0)
     for (int b = 0; b < g.B; ++b) {
-        cplx<T> acc[6][E];
+        cplx<T> acc[6][1][E];
 #pragma unroll
         for (int v = 0; v < 6; ++v)
 #pragma unroll
-            for (int m = 0; m < E; ++m) acc[v][m] = {T(0), T(0)};
+            for (int m = 0; m < E; ++m) acc[v][0][m] = {T(0), T(0)};
         // channels in groups of three (one line direction): unrolled inside a
         // group, a runtime loop over the groups
         for (int l = 0; l < NC / 3; ++l) {
@@ -257,7 +275,7 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
                 const int ch = 3 * l + gq;
                 const bool more = gq < 2 || l + 1 < NC / 3;
                 if (more) DDS_LOAD_RHO(nxt, b, ch + 1)
-                fft_regs<T, N, E, true>(cur, lds, lay, c, j, twN);
+                fft_regs_k<T, N, E, true, HZ, 1>(cur, twr, lds, 0, lay, c, j);
 #pragma unroll
                 for (int v = 0; v < 6; ++v) {
                     // signs of mirrored spectrum rows (wave-uniform)
@@ -267,14 +285,14 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
 #pragma unroll
                     for (int m = 0; m < E; ++m) {
                         const T sval = ((zc && 2 * m >= E) ? sz : sy) * sv[v][m];
-                        acc[v][m].x -= sval * cur[m].y;
-                        acc[v][m].y += sval * cur[m].x;
+                        acc[v][0][m].x -= sval * cur[0][m].y;
+                        acc[v][0][m].y += sval * cur[0][m].x;
                     }
                 }
                 if (more) {
                     DDS_LOAD_SPEC(sv, ch + 1)
 #pragma unroll
-                    for (int m = 0; m < E; ++m) cur[m] = nxt[m];
+                    for (int m = 0; m < EH; ++m) cur[0][m] = nxt[0][m];
                 }
             }
         }
@@ -286,13 +304,158 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
 #undef DDS_LOAD_SPEC
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            fft_regs<T, N, E, false>(acc[v], lds, lay, c, j, twN);
+            fft_regs_k<T, N, E, false, false, 1>(acc[v], twr, lds, 0, lay, c, j);
             if (valid) {
                 cplx<T>* dst = out_b + (int64_t)(b * 6 + v) * g.oqs;
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
+                for (int m = 0; m < EH; ++m) {
                     const int z = j + Tc * m;
-                    if (z < g.nz) dst[z * ors] = acc[v][m];
+                    if (z < g.nz) dst[z * ors] = acc[v][0][m];
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Fused z pass, grouped form. A block owns `tk` consecutive kx columns at one
+// ky and one group of Tc * tk threads per density channel (G = C groups). For
+// every realisation b:
+//   1. group g transforms channel g along z (length N; rows z >= N/2 are the
+//      zero padding and are not loaded) and puts rho^_g(kz) in LDS;
+//   2. group g forms the stress spectra of its components (v = 2g, 2g + 1
+//      when C = 3, v = g otherwise),
+//          sigma^_v(k) = sum_c i S_{v,c}(k) rho^_c(k)      (K^ = i S, K odd),
+//      summing over c in increasing order, and transforms them back along z,
+//      keeping rows z < nz. With C = 9 the groups g >= 6 have no component;
+//      they transform zeros alongside, to keep the block's barriers, and
+//      store nothing.
+// A group's transforms share their barriers, and a thread's spectrum values
+// (components x C x E numbers) stay in registers for all realisations. The
+// spectrum tile of the block is stored contiguously as [c][v][kz][tk]. The
+// density is requested before the spectrum values, so the first transform
+// waits for it alone, and the next realisation's density before the inverse
+// transforms, so its latency overlaps them.
+// ----------------------------------------------------------------------------
+template <typename T, int N, int E, int NC>
+__global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                   const T* __restrict__ spec, ZGeom g,
+                                                   const cplx<T>* __restrict__ tw, int tk, int ld) {
+    constexpr int Tc = N / E;
+    constexpr int OPG = NC == 3 ? 2 : 1;   // stress components per group
+    constexpr int EH = (E + 1) / 2;        // elements that can hold data rows (z < N/2)
+    constexpr bool HZ = N > 1;             // the upper half of every input column is padding
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int per = tk * Tc;
+    const int grp = threadIdx.x / per;
+    const int t = threadIdx.x - grp * per;
+    const int c = t % tk;
+    const int j = t / tk;
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int tile = blk % g.ntiles;
+    const int ky = blk / g.ntiles;
+    const int col = tile * tk + c;
+    const bool valid = col < g.ncols;
+    const int colc = valid ? col : 0;
+    const bool has_v = OPG * grp < 6;      // wave-uniform
+    const ColMajor lay{ld};
+    const int region = N * ld;             // one transform column block in LDS
+
+    // density rows z < nz of the block's columns; rows >= nz lie beyond the
+    // resource and read as zero. Lanes of padding columns (col >= ncols) read
+    // the tile's first column, which is valid.
+    const cplx<T>* in_g = in + (int64_t)ky * g.ios + (int64_t)tile * tk + (int64_t)grp * g.iqs;
+    const int64_t in_real = (int64_t)g.C * g.iqs;
+    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
+    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
+    const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
+    const int ors = (int)g.ors;                      // in-block offsets fit in 32 bits
+    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
+
+    cplx<T> fw[1][E];
+    {
+        const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_g, plane_bytes);
+#pragma unroll
+        for (int m = 0; m < EH; ++m) fw[0][m] = buf_cplx<T>(rr, r_lane, m * r_step);
+    }
+    constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
+    cplx<T> twr[TWC];
+    load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
+
+    // Spectrum values of this thread: its components, all channels, elements
+    // kz = j + Tc m. With a y mirror only ky <= Py/2 is stored and row Py - ky
+    // stands in for ky > Py/2; with a z mirror only kz <= N/2 is stored and
+    // elements m >= E/2 read kz' = N - kz = (Tc - j) + Tc (E - 1 - m). Odd
+    // planes change sign; the signs are applied once, here.
+    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
+    const int kyc = flip_y ? g.nky - ky : ky;
+    const bool zc = g.nkz_s < N;
+    const int nkz = g.nkz_s;
+    T sv[OPG][NC][E];
+    {
+        const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * tk;
+        const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * tk * sizeof(T)));
+        const int s_lane = (j * tk + c) * (int)sizeof(T);
+        const int s_lane_m = ((Tc - j) * tk + c) * (int)sizeof(T);
+#pragma unroll
+        for (int k = 0; k < OPG; ++k)
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) {
+                const int v = has_v ? OPG * grp + k : 0;
+                const int bit = ch * 6 + v;
+                const T sy = (flip_y && ((g.sgn_y >> bit) & 1)) ? T(-1) : T(1);
+                const T sz = ((g.sgn_z >> bit) & 1) ? -sy : sy;
+                const int base = (ch * 6 + v) * nkz;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const bool mir = zc && (2 * m >= E);
+                    const T val = buf_real<T>(srs, mir ? s_lane_m : s_lane,
+                                              (base + (mir ? Tc * (E - 1 - m) : Tc * m)) * tk * (int)sizeof(T));
+                    sv[k][ch][m] = (mir ? sz : sy) * val;
+                }
+            }
+    }
+
+    for (int b = 0; b < g.B; ++b) {
+        // 1. forward transform of channel grp; its spectrum to LDS region grp
+        fft_regs_k<T, N, E, true, HZ, 1>(fw, twr, lds + grp * region, region, lay, c, j);
+        __syncthreads();                             // the last stage's LDS reads are done
+#pragma unroll
+        for (int m = 0; m < E; ++m) lds[grp * region + lay(j + Tc * m, c)] = fw[0][m];
+        __syncthreads();
+        // 2. contraction for this group's components
+        cplx<T> acc[OPG][E];
+#pragma unroll
+        for (int k = 0; k < OPG; ++k)
+#pragma unroll
+            for (int m = 0; m < E; ++m) acc[k][m] = {T(0), T(0)};
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const cplx<T> r = lds[ch * region + lay(j + Tc * m, c)];
+#pragma unroll
+                for (int k = 0; k < OPG; ++k) {
+                    acc[k][m].x -= sv[k][ch][m] * r.y;
+                    acc[k][m].y += sv[k][ch][m] * r.x;
+                }
+            }
+        if (b + 1 < g.B) {
+            const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_g + (b + 1) * in_real, plane_bytes);
+#pragma unroll
+            for (int m = 0; m < EH; ++m) fw[0][m] = buf_cplx<T>(rr, r_lane, m * r_step);
+        }
+        // inverse transforms (their first stage's barrier precedes any LDS write)
+        fft_regs_k<T, N, E, false, false, OPG>(acc, twr, lds + OPG * grp * region, region, lay, c, j);
+        if (valid && has_v) {
+#pragma unroll
+            for (int k = 0; k < OPG; ++k) {
+                cplx<T>* dst = out_b + (int64_t)(b * 6 + OPG * grp + k) * g.oqs;
+#pragma unroll
+                for (int m = 0; m < EH; ++m) {
+                    const int z = j + Tc * m;
+                    if (z < g.nz) dst[z * ors] = acc[k][m];
                 }
             }
         }
@@ -303,18 +466,53 @@ __global__ void __launch_bounds__(512) k_z_fused(const cplx<T>* __restrict__ in,
 // Launch geometry and dispatch. A transform of length N runs with
 // E = min(N, ev) elements per thread, where the element class ev is a tuning
 // choice (it also bounds the radix, R <= E): 8 or 16 for the x and y passes;
-// 4 (FP32) or 2 (FP64) for the fused z pass, which keeps six accumulators,
-// the next channel's spectrum values and density column per element in
-// registers (larger classes spill).
+// 4 (FP32) or 2 (FP64) for the fused z pass, whose threads keep their
+// spectrum values and accumulators per element in registers. Long z
+// transforms (N >= 256) with many channels also take 2, 4 or 8 times that
+// class, so that one column per group fits a block.
 // ----------------------------------------------------------------------------
 static int ecount(int N, int ev) { return N < ev ? N : ev; }
 int x_threads(int M, int rows, int ev) { return rows * (M / ecount(M, ev)); }
 int col_threads(int N, int tk, int ev) { return tk * (N / ecount(N, ev)); }
-int z_threads(int N, int tk, int ev) { return tk * (N / ecount(N, ev)); }
+// Threads of a fused z block: `groups` groups (1, or one per density channel)
+// of tk x N/E threads.
+int z_threads(int N, int groups, int tk, int ev) { return groups * tk * (N / ecount(N, ev)); }
+int z_max_threads(int groups) { return groups == 1 ? 512 : 768; }
+bool z_groups_ok(int groups, int C) { return groups == 1 || groups == C; }
+// Many realisations amortise the grouped form's larger blocks.
+int default_z_groups(int C, int B) { return B >= 16 ? C : 1; }
+
+// LDS column stride of the fused z kernels (one column block per tile).
+int z_lds_ld(int tk, int elem_bytes) {
+    (void)elem_bytes;
+    return tk;
+}
+
+// LDS of a fused z block, in N x ld column blocks: the single-group form
+// exchanges through one; the grouped form keeps one per channel or per stress
+// component, whichever are more (the regions are reused).
+size_t z_lds_bytes(int N, int tk, int C, int groups, int elem_bytes) {
+    const int regions = groups == 1 ? 1 : (C > 6 ? C : 6);
+    return (size_t)regions * N * z_lds_ld(tk, elem_bytes) * 2 * elem_bytes;
+}
 int default_ev_col(int N) { return N <= 64 ? 8 : 16; }
-int default_ev_z(int elem_bytes) { return elem_bytes <= 4 ? 4 : 2; }
+static int base_ev_z(int elem_bytes) { return elem_bytes <= 4 ? 4 : 2; }
+constexpr int kLongZ = 256;              // shortest z length with the larger classes
+
+bool ev_z_ok(int N, int ev, int elem_bytes) {
+    const int b = base_ev_z(elem_bytes);
+    if (ev == b) return true;
+    return N >= kLongZ && ev <= 16 && (ev == 2 * b || ev == 4 * b || ev == 8 * b);
+}
+
+// The base class, or the smallest larger one with which a block of one
+// column per group fits.
+int default_ev_z(int N, int groups, int elem_bytes) {
+    int ev = base_ev_z(elem_bytes);
+    while (z_threads(N, groups, 1, ev) > z_max_threads(groups) && ev_z_ok(N, 2 * ev, elem_bytes)) ev *= 2;
+    return ev;
+}
 bool ev_col_ok(int ev) { return ev == 8 || ev == 16; }
-bool ev_z_ok(int ev, int elem_bytes) { return elem_bytes <= 4 ? ev == 4 : ev == 2; }
 
 int default_col_tk(int N, int elem_bytes) {
     const int tc = N / ecount(N, default_ev_col(N));
@@ -327,25 +525,48 @@ int default_col_tk(int N, int elem_bytes) {
 }
 
 int default_rows(int M, int elem_bytes) {
-    const int tc = M / ecount(M, default_ev_col(M));
+    const int e = ecount(M, default_ev_col(M));
+    const int tc = M / e;
+    const int ld = x_lds_ld(M, e, elem_bytes);
     int rows = 256 / tc;
     if (rows < 1) rows = 1;
-    while (rows > 1 && (int64_t)rows * (M + 1) * 2 * elem_bytes > 64 * 1024) rows /= 2;
+    while (rows > 1 && (int64_t)rows * ld * 2 * elem_bytes > 64 * 1024) rows /= 2;
     return rows;
 }
 
-int default_z_tk(int N, int elem_bytes) {
-    const int tc = N / ecount(N, default_ev_z(elem_bytes));
-    const int tk_min = elem_bytes <= 4 ? 16 : 8;
-    int tk = 256 / tc;
-    if (tk < tk_min) tk = tk_min;
-    while (tk > 1 && tk * tc > 512) tk /= 2;
-    while (tk > 1 && (int64_t)N * tk * 2 * elem_bytes > 64 * 1024) tk /= 2;
+int default_z_tk(int N, int C, int groups, int elem_bytes) {
+    const int tc = N / ecount(N, default_ev_z(N, groups, elem_bytes));
+    int tk;
+    if (groups == 1) {
+        const int tk_min = elem_bytes <= 4 ? 16 : 8;
+        tk = 256 / tc;
+        if (tk < tk_min) tk = tk_min;
+    } else {
+        tk = 128 / tc;
+    }
+    if (tk < 1) tk = 1;
+    while (tk > 1 && (z_lds_bytes(N, tk, C, groups, elem_bytes) > 64 * 1024 ||
+                      z_threads(N, groups, tk, ecount(N, default_ev_z(N, groups, elem_bytes))) > z_max_threads(groups)))
+        tk /= 2;
     return tk;
 }
 
 #define DDS_FOR_LENGTHS(X, EV) X(1, EV) X(2, EV) X(4, EV) X(8, EV) X(16, EV) X(32, EV) X(64, EV) \
     X(128, EV) X(256, EV) X(512, EV) X(1024, EV)
+
+// LDS row stride of the x passes: at least M + 1 elements and, when a wave
+// spans several rows, congruent to the threads per row modulo the elements of
+// one 256-byte bank window, so that the rows a wave touches fall on disjoint
+// banks.
+int x_lds_ld(int M, int E, int elem_bytes) {
+    const int es = 2 * elem_bytes;
+    const int win = 256 / es;
+    const int tc = M / E;
+    int ld = M + 1;
+    if (tc * es >= 256) return ld;
+    while (ld % win != tc % win) ++ld;
+    return ld;
+}
 
 // Real rows can be accessed in pairs when every row starts on a pair boundary.
 template <typename T>
@@ -358,13 +579,14 @@ static void x_r2c_ev(int M, const T* in, cplx<T>* out, int64_t nrows, int n_in, 
                      int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
     const int64_t blocks = (nrows + rows - 1) / rows;
     const int pairs = pairs_ok(in, in_stride, n_in);
-    const size_t lds = (size_t)rows * (M + 1) * sizeof(cplx<T>);
     switch (M) {
 #define X_CASE(L, EVV)                                                                                     \
     case L: {                                                                                              \
         constexpr int E = L < EVV ? L : EVV;                                                               \
+        const int ld = x_lds_ld(L, E, (int)sizeof(T));                                                     \
+        const size_t lds = (size_t)rows * ld * sizeof(cplx<T>);                                            \
         hipLaunchKernelGGL((k_x_r2c<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, in, out, \
-                           nrows, n_in, in_stride, out_stride, tw, rows, pairs);                           \
+                           nrows, n_in, in_stride, out_stride, tw, rows, pairs, ld);                           \
         break;                                                                                             \
     }
         DDS_FOR_LENGTHS(X_CASE, EV)
@@ -378,13 +600,14 @@ static void x_c2r_ev(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out,
                      int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
     const int64_t blocks = (nrows + rows - 1) / rows;
     const int pairs = pairs_ok(out, out_stride, n_out);
-    const size_t lds = (size_t)rows * (M + 1) * sizeof(cplx<T>);
     switch (M) {
 #define X_CASE(L, EVV)                                                                                     \
     case L: {                                                                                              \
         constexpr int E = L < EVV ? L : EVV;                                                               \
+        const int ld = x_lds_ld(L, E, (int)sizeof(T));                                                     \
+        const size_t lds = (size_t)rows * ld * sizeof(cplx<T>);                                            \
         hipLaunchKernelGGL((k_x_c2r<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, in, out, \
-                           nrows, n_out, in_stride, out_stride, tw, rows, pairs);                          \
+                           nrows, n_out, in_stride, out_stride, tw, rows, pairs, ld);                          \
         break;                                                                                             \
     }
         DDS_FOR_LENGTHS(X_CASE, EV)
@@ -411,21 +634,55 @@ static void col_ev(int N, const cplx<T>* in, cplx<T>* out, const ColGeom& g, con
     }
 }
 
-template <typename T, int EV, int NC>
+template <typename T, int L, int E, int NC, bool GROUPED>
+static void z_launch(int64_t blocks, int tk, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+                     const cplx<T>* tw, hipStream_t s) {
+    const int groups = GROUPED ? NC : 1;
+    const size_t lds = z_lds_bytes(L, tk, NC, groups, (int)sizeof(T));
+    const int ld = z_lds_ld(tk, (int)sizeof(T));
+    const dim3 block(groups * tk * (L / E));
+    if constexpr (GROUPED)
+        hipLaunchKernelGGL((k_z_grouped<T, L, E, NC>), dim3((unsigned)blocks), block, lds, s, in, out, spec, g, tw, tk, ld);
+    else
+        hipLaunchKernelGGL((k_z_serial<T, L, E, NC>), dim3((unsigned)blocks), block, lds, s, in, out, spec, g, tw, tk, ld);
+}
+
+template <typename T, int EV, int NC, bool GROUPED>
 static void z_ev(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g, const cplx<T>* tw,
                  int tk, int64_t blocks, hipStream_t s) {
-    const size_t lds = (size_t)N * tk * sizeof(cplx<T>);
     switch (N) {
 #define Z_CASE(L, EVV)                                                                                     \
-    case L: {                                                                                              \
-        constexpr int E = L < EVV ? L : EVV;                                                               \
-        hipLaunchKernelGGL((k_z_fused<T, L, E, NC>), dim3((unsigned)blocks), dim3(tk * (L / E)), lds, s, in, \
-                           out, spec, g, tw, tk);                                                          \
-        break;                                                                                             \
-    }
+    case L: z_launch<T, L, (L < EVV ? L : EVV), NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
         DDS_FOR_LENGTHS(Z_CASE, EV)
 #undef Z_CASE
         default: fail(DDSTRESS_E_UNSUPPORTED, "z transform length not supported");
+    }
+}
+
+// Larger element classes, instantiated for the long z lengths only.
+template <typename T, int EV, int NC, bool GROUPED>
+static void z_ev_long(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g, const cplx<T>* tw,
+                      int tk, int64_t blocks, hipStream_t s) {
+    switch (N) {
+        case 256: z_launch<T, 256, EV, NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
+        case 512: z_launch<T, 512, EV, NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
+        case 1024: z_launch<T, 1024, EV, NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
+        default: fail(DDSTRESS_E_UNSUPPORTED, "z transform length not supported");
+    }
+}
+
+template <typename T, int NC, bool GROUPED>
+static void z_dispatch(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+                       const cplx<T>* tw, int tk, int64_t blocks, hipStream_t s) {
+    constexpr int EV = sizeof(T) == 4 ? 4 : 2;
+    if (ev == EV) z_ev<T, EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
+    else if (ev == 2 * EV) z_ev_long<T, 2 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
+    else if (ev == 4 * EV) z_ev_long<T, 4 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
+    else if constexpr (8 * EV <= 16) {
+        if (ev == 8 * EV) z_ev_long<T, 8 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
+        else fail(DDSTRESS_E_INVALID, "z element class not supported");
+    } else {
+        fail(DDSTRESS_E_INVALID, "z element class not supported");
     }
 }
 
@@ -465,16 +722,31 @@ void launch_col_fft(int N, int ev, bool forward, const cplx<T>* in, cplx<T>* out
 }
 
 template <typename T>
-void launch_z_fused(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+void launch_z_fused(int N, int ev, int groups, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
                     const cplx<T>* tw, int tk, hipStream_t s) {
     const int64_t blocks = (int64_t)g.ntiles * g.nky;
     if (blocks <= 0) return;
-    if (!ev_z_ok(ev, (int)sizeof(T))) fail(DDSTRESS_E_INVALID, "z element class not supported for this precision");
-    constexpr int EV = sizeof(T) == 4 ? 4 : 2;
-    switch (g.C) {     // the channel loop is unrolled: one instance per line count
-        case 3: z_ev<T, EV, 3>(N, in, out, spec, g, tw, tk, blocks, s); break;
-        case 6: z_ev<T, EV, 6>(N, in, out, spec, g, tw, tk, blocks, s); break;
-        case 9: z_ev<T, EV, 9>(N, in, out, spec, g, tw, tk, blocks, s); break;
+    if (blocks > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
+    if (!ev_z_ok(N, ev, (int)sizeof(T))) fail(DDSTRESS_E_INVALID, "z element class not supported for this length");
+    if (!z_groups_ok(groups, g.C)) fail(DDSTRESS_E_INVALID, "z thread groups must be 1 or the channel count");
+    if (tk < 1 || z_threads(N, groups, tk, ev) > z_max_threads(groups) ||
+        z_lds_bytes(N, tk, g.C, groups, (int)sizeof(T)) > 64 * 1024)
+        fail(DDSTRESS_E_INVALID, "fused z block exceeds the thread or LDS limit");
+    // one instance per channel count: the channel loops are unrolled
+    const bool grouped = groups != 1;
+    switch (g.C) {
+        case 3:
+            grouped ? z_dispatch<T, 3, true>(N, ev, in, out, spec, g, tw, tk, blocks, s)
+                    : z_dispatch<T, 3, false>(N, ev, in, out, spec, g, tw, tk, blocks, s);
+            break;
+        case 6:
+            grouped ? z_dispatch<T, 6, true>(N, ev, in, out, spec, g, tw, tk, blocks, s)
+                    : z_dispatch<T, 6, false>(N, ev, in, out, spec, g, tw, tk, blocks, s);
+            break;
+        case 9:
+            grouped ? z_dispatch<T, 9, true>(N, ev, in, out, spec, g, tw, tk, blocks, s)
+                    : z_dispatch<T, 9, false>(N, ev, in, out, spec, g, tw, tk, blocks, s);
+            break;
         default: fail(DDSTRESS_E_INVALID, "channel count must be 3, 6 or 9");
     }
     check_hip(hipGetLastError(), "fused z launch");
@@ -487,8 +759,8 @@ void launch_z_fused(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spe
                                   int, hipStream_t);                                                       \
     template void launch_col_fft<T>(int, int, bool, const cplx<T>*, cplx<T>*, const ColGeom&, const cplx<T>*, \
                                     int, hipStream_t);                                                     \
-    template void launch_z_fused<T>(int, int, const cplx<T>*, cplx<T>*, const T*, const ZGeom&, const cplx<T>*, \
-                                    int, hipStream_t);
+    template void launch_z_fused<T>(int, int, int, const cplx<T>*, cplx<T>*, const T*, const ZGeom&,          \
+                                    const cplx<T>*, int, hipStream_t);
 INSTANTIATE(float)
 INSTANTIATE(double)
 #undef INSTANTIATE

@@ -76,15 +76,15 @@ def test_autotuned_plan(tmp_path):
     path = str(tmp_path / "tune.json")
     t = tuning.get_tuning(desc, path=path)
     assert t.rows_x >= 1 and t.tk_y >= 1 and t.tk_z >= 1 and all(v > 0 for v in t.ms)
-    assert t.ex in (8, 16) and t.ey in (8, 16) and t.ez == 4
+    assert t.ex in (8, 16) and t.ey in (8, 16) and t.ez == 4 and t.z_groups in (1, 6)
     data = json.load(open(path))
     assert len(data) == 1 and list(data.values())[0]["tk_z"] == t.tk_z
     again = tuning.get_tuning(desc, path=path)             # cache hit
     assert (again.rows_x, again.tk_y, again.tk_z, again.ez) == (t.rows_x, t.tk_y, t.tk_z, t.ez)
     tuned = tuning.tuned_plan(desc, path=path)
     info = tuned.info()
-    assert (info.rows_x, info.tile_y, info.tile_z, info.ex, info.ey, info.ez) == \
-        (t.rows_x, t.tk_y, t.tk_z, t.ex, t.ey, t.ez)
+    assert (info.rows_x, info.tile_y, info.tile_z, info.ex, info.ey, info.ez, info.z_groups) == \
+        (t.rows_x, t.tk_y, t.tk_z, t.ex, t.ey, t.ez, t.z_groups)
     plain = B.Plan(desc)
     rho = torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32)
     a = plain.new_output()
@@ -96,7 +96,7 @@ def test_autotuned_plan(tmp_path):
     torch.cuda.synchronize()
     assert (torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(a.double())).item() < 1e-6
     shared = tuned.share(2)                                 # a shared plan keeps the tuned launch shapes
-    assert shared.info().tile_z == t.tk_z and shared.info().ez == t.ez
+    assert shared.info().tile_z == t.tk_z and shared.info().ez == t.ez and shared.info().z_groups == t.z_groups
     c = torch.empty((1, 6, 12, 24, 40), dtype=torch.float32, device="cuda")
     shared.stress_batch(rho, c, 1)
     torch.cuda.synchronize()
@@ -106,7 +106,11 @@ def test_autotuned_plan(tmp_path):
 
 
 @pytest.mark.parametrize("precision", [32, 64])
-def test_tile_sizes_do_not_change_bits(precision):
+@pytest.mark.parametrize("groups", ["same", "other"])
+def test_tile_sizes_do_not_change_bits(precision, groups):
+    """Other tiles, and the other fused z form (one thread group per tile or
+    one per channel), give the same bits: the channel sum runs in the same
+    order and the transforms are the same code."""
     import torch
     from paper_1804_01830_amd import binding as B
     w = W.random_field((40, 24, 12), n_lines=2, seed=9, d=(1.0, 1.0, 2.0))
@@ -116,7 +120,11 @@ def test_tile_sizes_do_not_change_bits(precision):
     t = B.Tuning()
     t.rows_x, t.tk_y, t.tk_z = max(1, d.rows_x // 2), max(1, d.tile_y // 2), max(1, d.tile_z // 2)
     t.ex, t.ey, t.ez = d.ex, d.ey, d.ez
+    t.z_groups = d.z_groups if groups == "same" else (d.channels if d.z_groups == 1 else 1)
+    if t.z_groups != 1:
+        t.tk_z = 2                      # a grouped block of 6 x 16 x 2 threads
     other = B.Plan(desc, tuning=t)
+    assert other.info().z_groups == t.z_groups
     dt = torch.float32 if precision == 32 else torch.float64
     rho = torch.from_numpy(w["rho"]).to("cuda", dtype=dt)
     a, b = plain.new_output(), other.new_output()
