@@ -315,10 +315,20 @@ def main():
     z_ms = r32["passes"]["z_fused"] / max(r32["calls"], 1)
     achieved = zbytes / (z_ms * 1e-3) / 1e9
     pbytes = path_bytes(r32["info"], w["n"], C, B, elem)
+    info32 = r32["info"]
+    kname = "k_z_grouped" if info32.z_groups > 1 else "k_z_serial"
+    from paper_1804_01830_amd import profiling as Pf
+    traffic = Pf.stored_traffic(os.path.join(ROOT, "profiles"), w["name"], B, kname)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_z_fused (forward z FFT + 6xC contraction + inverse z)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
+                "traffic_vs_algorithmic": None if traffic is None else round(traffic / zbytes, 3),
+                "kernel": kname, "kernel_does": "forward z FFT, 6 x C contraction with the kernel spectrum, "
+                                                "inverse z FFT (fused)",
                 "algorithmic_bytes_per_launch": int(zbytes), "avg_launch_ms": round(z_ms, 5)}
+    plan_info = {"padded": list(info32.padded), "tile_z": info32.tile_z, "ez": info32.ez,
+                 "z_groups": info32.z_groups, "mirror_y": info32.mirror_y, "mirror_z": info32.mirror_z,
+                 "rows_x": info32.rows_x, "tile_y": info32.tile_y, "ex": info32.ex, "ey": info32.ey}
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "cells/s", "n_gpus": 1,
         "steps": r32["steps"], "warmup": args.warmup, "ms_per_step": round(ms32, 5),
@@ -341,6 +351,7 @@ def main():
         "path_algorithmic_gbs": round(pbytes / (ms32 * 1e-3) / 1e9, 1),
         "plan_build_s": {"fp32": round(r32["plan_s"], 3), "fp64": round(r64["plan_s"], 3)},
         "roofline": roofline,
+        "plan_info": plan_info,
     }
     if base is not None:
         line["cpu_baseline"] = base

@@ -93,6 +93,18 @@ int z_lds_ld(int tk, int elem_bytes);
 bool z_groups_ok(int groups, int C);
 int default_z_groups(int C, int B);
 int z_max_threads(int groups);
+size_t z_stage_bytes(int tk, int C, int nkz, int elem_bytes);
+bool z_stage_spec(int N, int tk, int C, int nkz, int B, int elem_bytes);
+
+// Fused z launch for C = NC channels and one form (zfused.hpp; instantiated
+// per form and precision in z_serial_f32.hip, z_grouped_f64.hip, ...).
+template <typename T, int NC, bool GROUPED>
+void z_dispatch(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+                const cplx<T>* tw, int tk, int64_t blocks, hipStream_t s);
+
+// Every power-of-two transform length the passes support.
+#define DDS_FOR_LENGTHS(X, EV) X(1, EV) X(2, EV) X(4, EV) X(8, EV) X(16, EV) X(32, EV) X(64, EV) \
+    X(128, EV) X(256, EV) X(512, EV) X(1024, EV)
 
 // ---- kernel build (kernel_build.hip) ---------------------------------------
 struct KernelParams {

@@ -181,6 +181,17 @@ __device__ __forceinline__ cplx<double> buf_cplx<double>(__amdgpu_buffer_rsrc_t 
     return {__hiloint2double((int)v[1], (int)v[0]), __hiloint2double((int)v[3], (int)v[2])};
 }
 
+// The hardware hands consecutive workgroups of a launch to the eight XCDs in
+// turn, and each XCD has its own L2. Logical block index of workgroup b of nb
+// such that every XCD works through one contiguous range of logical blocks
+// (neighbouring column tiles, which share cache lines, then meet in one L2).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int x = b % X, i = b / X;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 // Elements per thread used for a transform of length N in the plain passes.
 constexpr int elems_for(int N) { return N <= 8 ? N : (N <= 64 ? 8 : 16); }
 // Elements per thread in the fused z kernel (six complex accumulators per

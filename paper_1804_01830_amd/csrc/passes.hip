@@ -1,3 +1,5 @@
+// The x and y passes and the host-side launch rules of all passes; the fused
+// z kernels are in zfused.hpp (compiled in separate units).
 // The five passes of one stress evaluation (zero-padded convolution of
 // Eq. (10) by the convolution theorem, Sec. 2.3):
 //   x: real-to-complex along x      (rows contiguous)
@@ -12,16 +14,6 @@
 
 namespace dds {
 
-// The hardware hands consecutive workgroups of a launch to the eight XCDs in
-// turn, and each XCD has its own L2. Logical block index of workgroup b of nb
-// such that every XCD works through one contiguous range of logical blocks
-// (neighbouring column tiles, which share cache lines, then meet in one L2).
-__device__ __forceinline__ int xcd_block(int b, int nb) {
-    constexpr int X = 8;
-    const int q = nb / X, r = nb % X;
-    const int x = b % X, i = b / X;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
-}
 
 // ----------------------------------------------------------------------------
 // x: real-to-complex of length P = 2M. Row r has n_in reals (the rest of the P
@@ -184,285 +176,6 @@ __global__ void __launch_bounds__(512) k_col_fft(const cplx<T>* in, cplx<T>* out
 }
 
 // ----------------------------------------------------------------------------
-// Fused z pass, single-group form. A block owns `tk` consecutive kx columns at
-// one ky and one group of Tc * tk threads. For every realisation b it
-// transforms the C density columns along z one after the other (rows
-// z >= N/2 are the zero padding and are not loaded), accumulates the six
-// stress spectra
-//     sigma^_v(k) = sum_c i S_{v,c}(k) rho^_c(k)      (K^ = i S, K odd)
-// in registers, summing the channels in increasing order (the same arithmetic
-// as the grouped form), and transforms each back along z, writing rows
-// z < nz. The density column and spectrum values of the next channel (or of
-// the next realisation's first channel) are requested before the current
-// transform, so their latency overlaps the FFT work. Fewer threads per column
-// than the grouped form: better for few realisations.
-// ----------------------------------------------------------------------------
-template <typename T, int N, int E, int NC>
-__global__ void __launch_bounds__(512) k_z_serial(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-                                                  const T* __restrict__ spec, ZGeom g,
-                                                  const cplx<T>* __restrict__ tw, int tk, int ld) {
-    constexpr int Tc = N / E;
-    constexpr int EH = (E + 1) / 2;        // elements that can hold data rows (z < N/2)
-    constexpr bool HZ = N > 1;             // the upper half of every input column is padding
-    extern __shared__ unsigned char smem_raw[];
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int c = threadIdx.x % tk;
-    const int j = threadIdx.x / tk;
-    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int tile = blk % g.ntiles;
-    const int ky = blk / g.ntiles;
-    const int col = tile * tk + c;
-    const bool valid = col < g.ncols;
-    const int colc = valid ? col : 0;
-    const ColMajor lay{ld};
-    constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
-    cplx<T> twr[TWC];
-    load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
-    const int ors = (int)g.ors;
-    // Spectrum tile of this block: [c][v][kzc][tk] at row kyc. With a y mirror
-    // only ky <= Py/2 is stored and row Py - ky stands in for ky > Py/2; with
-    // a z mirror only kz <= N/2 is stored and elements m >= E/2 read
-    // kz' = N - kz = (Tc - j) + Tc (E - 1 - m). Odd planes change sign.
-    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
-    const int kyc = flip_y ? g.nky - ky : ky;
-    const bool zc = g.nkz_s < N;
-    const int nkz = g.nkz_s;
-    const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * tk;
-    const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * tk * sizeof(T)));
-    const int s_lane = (j * tk + c) * (int)sizeof(T);
-    const int s_lane_m = ((Tc - j) * tk + c) * (int)sizeof(T);
-    // density rows z < nz of the block's columns; rows >= nz lie beyond the
-    // resource and read as zero. Lanes of padding columns (col >= ncols) read
-    // the tile's first column, which is valid.
-    const cplx<T>* in_b = in + (int64_t)ky * g.ios + (int64_t)tile * tk;
-    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
-    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
-    const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
-    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
-
-#define DDS_LOAD_RHO(DST, BB, CH)                                                          \
-    {                                                                                      \
-        const __amdgpu_buffer_rsrc_t rr_ = make_rsrc(in_b + (int64_t)((BB) * g.C + (CH)) * g.iqs, plane_bytes); \
-        _Pragma("unroll") for (int m = 0; m < EH; ++m) DST[0][m] = buf_cplx<T>(rr_, r_lane, m * r_step); \
-    }
-#define DDS_LOAD_SPEC(DST, CH)                                                             \
-    {                                                                                      \
-        _Pragma("unroll") for (int v = 0; v < 6; ++v) {                                    \
-            const int base_ = ((CH) * 6 + v) * nkz;                                        \
-            _Pragma("unroll") for (int m = 0; m < E; ++m) {                                \
-                const bool mir_ = zc && (2 * m >= E);      /* uniform: selects, no branch */ \
-                DST[v][m] = buf_real<T>(srs, mir_ ? s_lane_m : s_lane,                     \
-                                        (base_ + (mir_ ? Tc * (E - 1 - m) : Tc * m)) * tk * (int)sizeof(T)); \
-            }                                                                              \
-        }                                                                                  \
-    }
-
-    cplx<T> cur[1][E], nxt[1][E];
-    T sv[6][E];
-    DDS_LOAD_RHO(cur, 0, 0)
-    DDS_LOAD_SPEC(sv, 0)
-    for (int b = 0; b < g.B; ++b) {
-        cplx<T> acc[6][1][E];
-#pragma unroll
-        for (int v = 0; v < 6; ++v)
-#pragma unroll
-            for (int m = 0; m < E; ++m) acc[v][0][m] = {T(0), T(0)};
-        // channels in groups of three (one line direction): unrolled inside a
-        // group, a runtime loop over the groups
-        for (int l = 0; l < NC / 3; ++l) {
-#pragma unroll
-            for (int gq = 0; gq < 3; ++gq) {
-                const int ch = 3 * l + gq;
-                const bool more = gq < 2 || l + 1 < NC / 3;
-                if (more) DDS_LOAD_RHO(nxt, b, ch + 1)
-                fft_regs_k<T, N, E, true, HZ, 1>(cur, twr, lds, 0, lay, c, j);
-#pragma unroll
-                for (int v = 0; v < 6; ++v) {
-                    // signs of mirrored spectrum rows (wave-uniform)
-                    const int bit = ch * 6 + v;
-                    const T sy = (flip_y && ((g.sgn_y >> bit) & 1)) ? T(-1) : T(1);
-                    const T sz = ((g.sgn_z >> bit) & 1) ? -sy : sy;
-#pragma unroll
-                    for (int m = 0; m < E; ++m) {
-                        const T sval = ((zc && 2 * m >= E) ? sz : sy) * sv[v][m];
-                        acc[v][0][m].x -= sval * cur[0][m].y;
-                        acc[v][0][m].y += sval * cur[0][m].x;
-                    }
-                }
-                if (more) {
-                    DDS_LOAD_SPEC(sv, ch + 1)
-#pragma unroll
-                    for (int m = 0; m < EH; ++m) cur[0][m] = nxt[0][m];
-                }
-            }
-        }
-        if (b + 1 < g.B) {      // first channel of the next realisation
-            DDS_LOAD_RHO(cur, b + 1, 0)
-            DDS_LOAD_SPEC(sv, 0)
-        }
-#undef DDS_LOAD_RHO
-#undef DDS_LOAD_SPEC
-#pragma unroll
-        for (int v = 0; v < 6; ++v) {
-            fft_regs_k<T, N, E, false, false, 1>(acc[v], twr, lds, 0, lay, c, j);
-            if (valid) {
-                cplx<T>* dst = out_b + (int64_t)(b * 6 + v) * g.oqs;
-#pragma unroll
-                for (int m = 0; m < EH; ++m) {
-                    const int z = j + Tc * m;
-                    if (z < g.nz) dst[z * ors] = acc[v][0][m];
-                }
-            }
-        }
-    }
-}
-
-// ----------------------------------------------------------------------------
-// Fused z pass, grouped form. A block owns `tk` consecutive kx columns at one
-// ky and one group of Tc * tk threads per density channel (G = C groups). For
-// every realisation b:
-//   1. group g transforms channel g along z (length N; rows z >= N/2 are the
-//      zero padding and are not loaded) and puts rho^_g(kz) in LDS;
-//   2. group g forms the stress spectra of its components (v = 2g, 2g + 1
-//      when C = 3, v = g otherwise),
-//          sigma^_v(k) = sum_c i S_{v,c}(k) rho^_c(k)      (K^ = i S, K odd),
-//      summing over c in increasing order, and transforms them back along z,
-//      keeping rows z < nz. With C = 9 the groups g >= 6 have no component;
-//      they transform zeros alongside, to keep the block's barriers, and
-//      store nothing.
-// A group's transforms share their barriers, and a thread's spectrum values
-// (components x C x E numbers) stay in registers for all realisations. The
-// spectrum tile of the block is stored contiguously as [c][v][kz][tk]. The
-// density is requested before the spectrum values, so the first transform
-// waits for it alone, and the next realisation's density before the inverse
-// transforms, so its latency overlaps them.
-// ----------------------------------------------------------------------------
-template <typename T, int N, int E, int NC>
-__global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
-                                                   const T* __restrict__ spec, ZGeom g,
-                                                   const cplx<T>* __restrict__ tw, int tk, int ld) {
-    constexpr int Tc = N / E;
-    constexpr int OPG = NC == 3 ? 2 : 1;   // stress components per group
-    constexpr int EH = (E + 1) / 2;        // elements that can hold data rows (z < N/2)
-    constexpr bool HZ = N > 1;             // the upper half of every input column is padding
-    extern __shared__ unsigned char smem_raw[];
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-    const int per = tk * Tc;
-    const int grp = threadIdx.x / per;
-    const int t = threadIdx.x - grp * per;
-    const int c = t % tk;
-    const int j = t / tk;
-    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int tile = blk % g.ntiles;
-    const int ky = blk / g.ntiles;
-    const int col = tile * tk + c;
-    const bool valid = col < g.ncols;
-    const int colc = valid ? col : 0;
-    const bool has_v = OPG * grp < 6;      // wave-uniform
-    const ColMajor lay{ld};
-    const int region = N * ld;             // one transform column block in LDS
-
-    // density rows z < nz of the block's columns; rows >= nz lie beyond the
-    // resource and read as zero. Lanes of padding columns (col >= ncols) read
-    // the tile's first column, which is valid.
-    const cplx<T>* in_g = in + (int64_t)ky * g.ios + (int64_t)tile * tk + (int64_t)grp * g.iqs;
-    const int64_t in_real = (int64_t)g.C * g.iqs;
-    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
-    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
-    const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
-    const int ors = (int)g.ors;                      // in-block offsets fit in 32 bits
-    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
-
-    cplx<T> fw[1][E];
-    {
-        const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_g, plane_bytes);
-#pragma unroll
-        for (int m = 0; m < EH; ++m) fw[0][m] = buf_cplx<T>(rr, r_lane, m * r_step);
-    }
-    constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
-    cplx<T> twr[TWC];
-    load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
-
-    // Spectrum values of this thread: its components, all channels, elements
-    // kz = j + Tc m. With a y mirror only ky <= Py/2 is stored and row Py - ky
-    // stands in for ky > Py/2; with a z mirror only kz <= N/2 is stored and
-    // elements m >= E/2 read kz' = N - kz = (Tc - j) + Tc (E - 1 - m). Odd
-    // planes change sign; the signs are applied once, here.
-    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
-    const int kyc = flip_y ? g.nky - ky : ky;
-    const bool zc = g.nkz_s < N;
-    const int nkz = g.nkz_s;
-    T sv[OPG][NC][E];
-    {
-        const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * tk;
-        const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * tk * sizeof(T)));
-        const int s_lane = (j * tk + c) * (int)sizeof(T);
-        const int s_lane_m = ((Tc - j) * tk + c) * (int)sizeof(T);
-#pragma unroll
-        for (int k = 0; k < OPG; ++k)
-#pragma unroll
-            for (int ch = 0; ch < NC; ++ch) {
-                const int v = has_v ? OPG * grp + k : 0;
-                const int bit = ch * 6 + v;
-                const T sy = (flip_y && ((g.sgn_y >> bit) & 1)) ? T(-1) : T(1);
-                const T sz = ((g.sgn_z >> bit) & 1) ? -sy : sy;
-                const int base = (ch * 6 + v) * nkz;
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const bool mir = zc && (2 * m >= E);
-                    const T val = buf_real<T>(srs, mir ? s_lane_m : s_lane,
-                                              (base + (mir ? Tc * (E - 1 - m) : Tc * m)) * tk * (int)sizeof(T));
-                    sv[k][ch][m] = (mir ? sz : sy) * val;
-                }
-            }
-    }
-
-    for (int b = 0; b < g.B; ++b) {
-        // 1. forward transform of channel grp; its spectrum to LDS region grp
-        fft_regs_k<T, N, E, true, HZ, 1>(fw, twr, lds + grp * region, region, lay, c, j);
-        __syncthreads();                             // the last stage's LDS reads are done
-#pragma unroll
-        for (int m = 0; m < E; ++m) lds[grp * region + lay(j + Tc * m, c)] = fw[0][m];
-        __syncthreads();
-        // 2. contraction for this group's components
-        cplx<T> acc[OPG][E];
-#pragma unroll
-        for (int k = 0; k < OPG; ++k)
-#pragma unroll
-            for (int m = 0; m < E; ++m) acc[k][m] = {T(0), T(0)};
-#pragma unroll
-        for (int ch = 0; ch < NC; ++ch)
-#pragma unroll
-            for (int m = 0; m < E; ++m) {
-                const cplx<T> r = lds[ch * region + lay(j + Tc * m, c)];
-#pragma unroll
-                for (int k = 0; k < OPG; ++k) {
-                    acc[k][m].x -= sv[k][ch][m] * r.y;
-                    acc[k][m].y += sv[k][ch][m] * r.x;
-                }
-            }
-        if (b + 1 < g.B) {
-            const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_g + (b + 1) * in_real, plane_bytes);
-#pragma unroll
-            for (int m = 0; m < EH; ++m) fw[0][m] = buf_cplx<T>(rr, r_lane, m * r_step);
-        }
-        // inverse transforms (their first stage's barrier precedes any LDS write)
-        fft_regs_k<T, N, E, false, false, OPG>(acc, twr, lds + OPG * grp * region, region, lay, c, j);
-        if (valid && has_v) {
-#pragma unroll
-            for (int k = 0; k < OPG; ++k) {
-                cplx<T>* dst = out_b + (int64_t)(b * 6 + OPG * grp + k) * g.oqs;
-#pragma unroll
-                for (int m = 0; m < EH; ++m) {
-                    const int z = j + Tc * m;
-                    if (z < g.nz) dst[z * ors] = acc[k][m];
-                }
-            }
-        }
-    }
-}
-
-// ----------------------------------------------------------------------------
 // Launch geometry and dispatch. A transform of length N runs with
 // E = min(N, ev) elements per thread, where the element class ev is a tuning
 // choice (it also bounds the radix, R <= E): 8 or 16 for the x and y passes;
@@ -494,6 +207,19 @@ int z_lds_ld(int tk, int elem_bytes) {
 size_t z_lds_bytes(int N, int tk, int C, int groups, int elem_bytes) {
     const int regions = groups == 1 ? 1 : (C > 6 ? C : 6);
     return (size_t)regions * N * z_lds_ld(tk, elem_bytes) * 2 * elem_bytes;
+}
+
+// The single-group form stages its spectrum tile (nkz rows of (6C + 1) tk
+// values) in LDS for the compile-time widths tk = 4, 8, 16, when there are
+// realisations to reuse it (B >= 2) and the tile and the exchange block fit
+// 64 KiB together (z lengths up to 256; in FP64 with three channels only,
+// more would spill registers).
+size_t z_stage_bytes(int tk, int C, int nkz, int elem_bytes) {
+    return (size_t)nkz * (6 * C + 1) * tk * elem_bytes;
+}
+bool z_stage_spec(int N, int tk, int C, int nkz, int B, int elem_bytes) {
+    return B >= 2 && N <= 256 && (tk == 4 || tk == 8 || tk == 16) && (elem_bytes <= 4 || C == 3) &&
+           z_lds_bytes(N, tk, C, 1, elem_bytes) + z_stage_bytes(tk, C, nkz, elem_bytes) <= 64 * 1024;
 }
 int default_ev_col(int N) { return N <= 64 ? 8 : 16; }
 static int base_ev_z(int elem_bytes) { return elem_bytes <= 4 ? 4 : 2; }
@@ -551,8 +277,6 @@ int default_z_tk(int N, int C, int groups, int elem_bytes) {
     return tk;
 }
 
-#define DDS_FOR_LENGTHS(X, EV) X(1, EV) X(2, EV) X(4, EV) X(8, EV) X(16, EV) X(32, EV) X(64, EV) \
-    X(128, EV) X(256, EV) X(512, EV) X(1024, EV)
 
 // LDS row stride of the x passes: at least M + 1 elements and, when a wave
 // spans several rows, congruent to the threads per row modulo the elements of
@@ -631,58 +355,6 @@ static void col_ev(int N, const cplx<T>* in, cplx<T>* out, const ColGeom& g, con
         DDS_FOR_LENGTHS(C_CASE, EV)
 #undef C_CASE
         default: fail(DDSTRESS_E_UNSUPPORTED, "column transform length not supported");
-    }
-}
-
-template <typename T, int L, int E, int NC, bool GROUPED>
-static void z_launch(int64_t blocks, int tk, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
-                     const cplx<T>* tw, hipStream_t s) {
-    const int groups = GROUPED ? NC : 1;
-    const size_t lds = z_lds_bytes(L, tk, NC, groups, (int)sizeof(T));
-    const int ld = z_lds_ld(tk, (int)sizeof(T));
-    const dim3 block(groups * tk * (L / E));
-    if constexpr (GROUPED)
-        hipLaunchKernelGGL((k_z_grouped<T, L, E, NC>), dim3((unsigned)blocks), block, lds, s, in, out, spec, g, tw, tk, ld);
-    else
-        hipLaunchKernelGGL((k_z_serial<T, L, E, NC>), dim3((unsigned)blocks), block, lds, s, in, out, spec, g, tw, tk, ld);
-}
-
-template <typename T, int EV, int NC, bool GROUPED>
-static void z_ev(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g, const cplx<T>* tw,
-                 int tk, int64_t blocks, hipStream_t s) {
-    switch (N) {
-#define Z_CASE(L, EVV)                                                                                     \
-    case L: z_launch<T, L, (L < EVV ? L : EVV), NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
-        DDS_FOR_LENGTHS(Z_CASE, EV)
-#undef Z_CASE
-        default: fail(DDSTRESS_E_UNSUPPORTED, "z transform length not supported");
-    }
-}
-
-// Larger element classes, instantiated for the long z lengths only.
-template <typename T, int EV, int NC, bool GROUPED>
-static void z_ev_long(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g, const cplx<T>* tw,
-                      int tk, int64_t blocks, hipStream_t s) {
-    switch (N) {
-        case 256: z_launch<T, 256, EV, NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
-        case 512: z_launch<T, 512, EV, NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
-        case 1024: z_launch<T, 1024, EV, NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
-        default: fail(DDSTRESS_E_UNSUPPORTED, "z transform length not supported");
-    }
-}
-
-template <typename T, int NC, bool GROUPED>
-static void z_dispatch(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
-                       const cplx<T>* tw, int tk, int64_t blocks, hipStream_t s) {
-    constexpr int EV = sizeof(T) == 4 ? 4 : 2;
-    if (ev == EV) z_ev<T, EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
-    else if (ev == 2 * EV) z_ev_long<T, 2 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
-    else if (ev == 4 * EV) z_ev_long<T, 4 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
-    else if constexpr (8 * EV <= 16) {
-        if (ev == 8 * EV) z_ev_long<T, 8 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
-        else fail(DDSTRESS_E_INVALID, "z element class not supported");
-    } else {
-        fail(DDSTRESS_E_INVALID, "z element class not supported");
     }
 }
 

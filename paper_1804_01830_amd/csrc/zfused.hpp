@@ -1,0 +1,428 @@
+// Fused z kernels (single-group and grouped forms) and their launch
+// dispatch. Each form and precision is instantiated in a unit of its own
+// (z_serial_f32.hip, ...), so the many template instances compile in parallel.
+#pragma once
+
+#include "ddstress_internal.hpp"
+
+namespace dds {
+
+// ----------------------------------------------------------------------------
+// Fused z pass, single-group form. A block owns `tk` consecutive kx columns at
+// one ky and one group of Tc * tk threads. For every realisation b it
+// transforms the C density columns along z one after the other (rows
+// z >= N/2 are the zero padding and are not loaded), accumulates the six
+// stress spectra
+//     sigma^_v(k) = sum_c i S_{v,c}(k) rho^_c(k)      (K^ = i S, K odd)
+// in registers, summing the channels in increasing order (the same arithmetic
+// as the grouped form), and transforms each back along z, writing rows
+// z < nz. The density column of the next channel (or of the next
+// realisation's first channel) is requested before the current transform, so
+// its latency overlaps the FFT work.
+//
+// TK > 0 fixes the tile width at compile time: the block then copies its
+// spectrum tile once into LDS, as rows kz of [c][v][TK] values with a row
+// stride of (6C + 1) TK (the odd multiple of TK puts the rows a wave reads on
+// distinct banks), with the y-mirror sign applied, and every realisation reads
+// it there; all LDS offsets are immediates. TK = 0 takes the width at run time
+// and reads the spectrum from memory for each realisation. Fewer threads per
+// column than the grouped form: better for few realisations.
+// ----------------------------------------------------------------------------
+template <typename T, int N, int E, int NC, int TK>
+__global__ void __launch_bounds__(512) k_z_serial(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                  const T* __restrict__ spec, ZGeom g,
+                                                  const cplx<T>* __restrict__ tw, int tk_arg, int ld_arg) {
+    constexpr int Tc = N / E;
+    constexpr int EH = (E + 1) / 2;        // elements that can hold data rows (z < N/2)
+    constexpr bool HZ = N > 1;             // the upper half of every input column is padding
+    constexpr bool SL = TK > 0;            // spectrum staged in LDS
+    constexpr int KS = (6 * NC + 1) * (TK > 0 ? TK : 1);   // staged row stride (values)
+    const int tk = SL ? TK : tk_arg;
+    const int ld = SL ? TK : ld_arg;
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int c = threadIdx.x % tk;
+    const int j = threadIdx.x / tk;
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int tile = blk % g.ntiles;
+    const int ky = blk / g.ntiles;
+    const int col = tile * tk + c;
+    const bool valid = col < g.ncols;
+    const int colc = valid ? col : 0;
+    const ColMajor lay{ld};
+    const int ors = (int)g.ors;
+    // Spectrum tile of this block: [c][v][kzc][tk] at row kyc. With a y mirror
+    // only ky <= Py/2 is stored and row Py - ky stands in for ky > Py/2; with
+    // a z mirror only kz <= N/2 is stored and elements m >= E/2 read
+    // kz' = N - kz = (Tc - j) + Tc (E - 1 - m). Odd planes change sign.
+    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
+    const int kyc = flip_y ? g.nky - ky : ky;
+    const bool zc = g.nkz_s < N;
+    const int nkz = g.nkz_s;
+    const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * tk;
+    const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * tk * sizeof(T)));
+    const int s_lane = (j * tk + c) * (int)sizeof(T);
+    const int s_lane_m = ((Tc - j) * tk + c) * (int)sizeof(T);
+    // density rows z < nz of the block's columns; rows >= nz lie beyond the
+    // resource and read as zero. Lanes of padding columns (col >= ncols) read
+    // the tile's first column, which is valid.
+    const cplx<T>* in_b = in + (int64_t)ky * g.ios + (int64_t)tile * tk;
+    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
+    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
+    const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
+    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
+
+#define DDS_LOAD_RHO(DST, BB, CH)                                                          \
+    {                                                                                      \
+        const __amdgpu_buffer_rsrc_t rr_ = make_rsrc(in_b + (int64_t)((BB) * g.C + (CH)) * g.iqs, plane_bytes); \
+        _Pragma("unroll") for (int m = 0; m < EH; ++m) DST[0][m] = buf_cplx<T>(rr_, r_lane, m * r_step); \
+    }
+    cplx<T> cur[1][E], nxt[1][E];
+    DDS_LOAD_RHO(cur, 0, 0)
+    constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
+    cplx<T> twr[TWC];
+    load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
+
+    T* s_l = reinterpret_cast<T*>(smem_raw + (size_t)N * ld * sizeof(cplx<T>));
+    const T* s_lj = s_l + j * KS + c;               // staged row kz = j of this lane
+    const T* s_lm = s_l + (Tc - j) * KS + c;        // staged row kz = Tc - j (mirrored elements)
+    if constexpr (SL) {
+        // copy [c][v][kz][TK] -> rows kz of [c][v][TK] in 16-byte pieces: up to
+        // 16 loads per thread are in flight before their stores; a piece never
+        // straddles a source row (TK is a multiple of its width)
+        constexpr int VW = 16 / (int)sizeof(T);
+        constexpr int NT = TK * Tc;
+        constexpr int CH = 16;
+        const int n_vals = NC * 6 * nkz * TK;
+        const float rcp = 1.0f / (float)nkz;
+        for (int k0 = 0; k0 * NT * VW < n_vals; k0 += CH) {
+            uint4 piece[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k)
+                piece[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                                         srs, ((int)threadIdx.x + (k0 + k) * NT) * 16, 0, 0));
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int i = ((int)threadIdx.x + (k0 + k) * NT) * VW;    // first value of the piece
+                if (i < n_vals) {
+                    const int r = i / TK, cc = i % TK;
+                    int cv = (int)((float)r * rcp);
+                    if (cv * nkz > r) --cv;
+                    if ((cv + 1) * nkz <= r) ++cv;
+                    const int kz = r - cv * nkz;
+                    const bool neg = flip_y && ((g.sgn_y >> cv) & 1);      // cv = c 6 + v
+                    uint4 q = piece[k];
+                    if (neg) {                                              // flip the sign bits
+                        if constexpr (sizeof(T) == 4) {
+                            q.x ^= 0x80000000u; q.y ^= 0x80000000u; q.z ^= 0x80000000u; q.w ^= 0x80000000u;
+                        } else {
+                            q.y ^= 0x80000000u; q.w ^= 0x80000000u;
+                        }
+                    }
+                    *reinterpret_cast<uint4*>(s_l + kz * KS + cv * TK + cc) = q;
+                }
+            }
+        }
+        __syncthreads();
+    }
+#define DDS_LOAD_SPEC(DST, CH)                                                             \
+    {                                                                                      \
+        _Pragma("unroll") for (int v = 0; v < 6; ++v) {                                    \
+            const int base_ = ((CH) * 6 + v) * nkz;                                        \
+            _Pragma("unroll") for (int m = 0; m < E; ++m) {                                \
+                const bool mir_ = zc && (2 * m >= E);      /* uniform: selects, no branch */ \
+                if constexpr (SL)                                                          \
+                    DST[v][m] = mir_ ? s_lm[(Tc * (E - 1 - m)) * KS + ((CH) * 6 + v) * TK] \
+                                     : s_lj[(Tc * m) * KS + ((CH) * 6 + v) * TK];          \
+                else                                                                       \
+                    DST[v][m] = buf_real<T>(srs, mir_ ? s_lane_m : s_lane,                 \
+                                            (base_ + (mir_ ? Tc * (E - 1 - m) : Tc * m)) * tk * (int)sizeof(T)); \
+            }                                                                              \
+        }                                                                                  \
+    }
+
+    T sv[6][E];
+    DDS_LOAD_SPEC(sv, 0)
+    for (int b = 0; b < g.B; ++b) {
+        cplx<T> acc[6][1][E];
+#pragma unroll
+        for (int v = 0; v < 6; ++v)
+#pragma unroll
+            for (int m = 0; m < E; ++m) acc[v][0][m] = {T(0), T(0)};
+        // channels in groups of three (one line direction): unrolled inside a
+        // group, a runtime loop over the groups
+        for (int l = 0; l < NC / 3; ++l) {
+#pragma unroll
+            for (int gq = 0; gq < 3; ++gq) {
+                const int ch = 3 * l + gq;
+                const bool more = gq < 2 || l + 1 < NC / 3;
+                if (more) DDS_LOAD_RHO(nxt, b, ch + 1)
+                fft_regs_k<T, N, E, true, HZ, 1>(cur, twr, lds, 0, lay, c, j);
+#pragma unroll
+                for (int v = 0; v < 6; ++v) {
+                    // signs of mirrored spectrum rows (wave-uniform); staged
+                    // values already carry the y sign
+                    const int bit = ch * 6 + v;
+                    const T sy = (!SL && flip_y && ((g.sgn_y >> bit) & 1)) ? T(-1) : T(1);
+                    const T sz = ((g.sgn_z >> bit) & 1) ? -sy : sy;
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const T sval = (SL && !(zc && 2 * m >= E)) ? sv[v][m]
+                                                                    : ((zc && 2 * m >= E) ? sz : sy) * sv[v][m];
+                        acc[v][0][m].x -= sval * cur[0][m].y;
+                        acc[v][0][m].y += sval * cur[0][m].x;
+                    }
+                }
+                if (more) {
+                    DDS_LOAD_SPEC(sv, ch + 1)
+#pragma unroll
+                    for (int m = 0; m < EH; ++m) cur[0][m] = nxt[0][m];
+                }
+            }
+        }
+        if (b + 1 < g.B) {      // first channel of the next realisation
+            DDS_LOAD_RHO(cur, b + 1, 0)
+            DDS_LOAD_SPEC(sv, 0)
+        }
+#undef DDS_LOAD_RHO
+#undef DDS_LOAD_SPEC
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            fft_regs_k<T, N, E, false, false, 1>(acc[v], twr, lds, 0, lay, c, j);
+            if (valid) {
+                cplx<T>* dst = out_b + (int64_t)(b * 6 + v) * g.oqs;
+#pragma unroll
+                for (int m = 0; m < EH; ++m) {
+                    const int z = j + Tc * m;
+                    if (z < g.nz) dst[z * ors] = acc[v][0][m];
+                }
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Fused z pass, grouped form. A block owns `tk` consecutive kx columns at one
+// ky and one group of Tc * tk threads per density channel (G = C groups). For
+// every realisation b:
+//   1. group g transforms channel g along z (length N; rows z >= N/2 are the
+//      zero padding and are not loaded) and puts rho^_g(kz) in LDS;
+//   2. group g forms the stress spectra of its components (v = 2g, 2g + 1
+//      when C = 3, v = g otherwise),
+//          sigma^_v(k) = sum_c i S_{v,c}(k) rho^_c(k)      (K^ = i S, K odd),
+//      summing over c in increasing order, and transforms them back along z,
+//      keeping rows z < nz. With C = 9 the groups g >= 6 have no component;
+//      they transform zeros alongside, to keep the block's barriers, and
+//      store nothing.
+// A group's transforms share their barriers, and a thread's spectrum values
+// (components x C x E numbers) stay in registers for all realisations. The
+// spectrum tile of the block is stored contiguously as [c][v][kz][tk]. The
+// density is requested before the spectrum values, so the first transform
+// waits for it alone, and the next realisation's density before the inverse
+// transforms, so its latency overlaps them.
+// ----------------------------------------------------------------------------
+template <typename T, int N, int E, int NC>
+__global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                   const T* __restrict__ spec, ZGeom g,
+                                                   const cplx<T>* __restrict__ tw, int tk, int ld) {
+    constexpr int Tc = N / E;
+    constexpr int OPG = NC == 3 ? 2 : 1;   // stress components per group
+    constexpr int EH = (E + 1) / 2;        // elements that can hold data rows (z < N/2)
+    constexpr bool HZ = N > 1;             // the upper half of every input column is padding
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int per = tk * Tc;
+    const int grp = threadIdx.x / per;
+    const int t = threadIdx.x - grp * per;
+    const int c = t % tk;
+    const int j = t / tk;
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int tile = blk % g.ntiles;
+    const int ky = blk / g.ntiles;
+    const int col = tile * tk + c;
+    const bool valid = col < g.ncols;
+    const int colc = valid ? col : 0;
+    const bool has_v = OPG * grp < 6;      // wave-uniform
+    const ColMajor lay{ld};
+    const int region = N * ld;             // one transform column block in LDS
+
+    // density rows z < nz of the block's columns; rows >= nz lie beyond the
+    // resource and read as zero. Lanes of padding columns (col >= ncols) read
+    // the tile's first column, which is valid.
+    const cplx<T>* in_g = in + (int64_t)ky * g.ios + (int64_t)tile * tk + (int64_t)grp * g.iqs;
+    const int64_t in_real = (int64_t)g.C * g.iqs;
+    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
+    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
+    const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
+    const int ors = (int)g.ors;                      // in-block offsets fit in 32 bits
+    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
+
+    cplx<T> fw[1][E];
+    {
+        const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_g, plane_bytes);
+#pragma unroll
+        for (int m = 0; m < EH; ++m) fw[0][m] = buf_cplx<T>(rr, r_lane, m * r_step);
+    }
+    constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
+    cplx<T> twr[TWC];
+    load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
+
+    // Spectrum values of this thread: its components, all channels, elements
+    // kz = j + Tc m. With a y mirror only ky <= Py/2 is stored and row Py - ky
+    // stands in for ky > Py/2; with a z mirror only kz <= N/2 is stored and
+    // elements m >= E/2 read kz' = N - kz = (Tc - j) + Tc (E - 1 - m). Odd
+    // planes change sign; the signs are applied once, here.
+    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
+    const int kyc = flip_y ? g.nky - ky : ky;
+    const bool zc = g.nkz_s < N;
+    const int nkz = g.nkz_s;
+    T sv[OPG][NC][E];
+    {
+        const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * tk;
+        const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * tk * sizeof(T)));
+        const int s_lane = (j * tk + c) * (int)sizeof(T);
+        const int s_lane_m = ((Tc - j) * tk + c) * (int)sizeof(T);
+#pragma unroll
+        for (int k = 0; k < OPG; ++k)
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) {
+                const int v = has_v ? OPG * grp + k : 0;
+                const int bit = ch * 6 + v;
+                const T sy = (flip_y && ((g.sgn_y >> bit) & 1)) ? T(-1) : T(1);
+                const T sz = ((g.sgn_z >> bit) & 1) ? -sy : sy;
+                const int base = (ch * 6 + v) * nkz;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const bool mir = zc && (2 * m >= E);
+                    const T val = buf_real<T>(srs, mir ? s_lane_m : s_lane,
+                                              (base + (mir ? Tc * (E - 1 - m) : Tc * m)) * tk * (int)sizeof(T));
+                    sv[k][ch][m] = (mir ? sz : sy) * val;
+                }
+            }
+    }
+
+    for (int b = 0; b < g.B; ++b) {
+        // 1. forward transform of channel grp; its spectrum to LDS region grp
+        fft_regs_k<T, N, E, true, HZ, 1>(fw, twr, lds + grp * region, region, lay, c, j);
+        __syncthreads();                             // the last stage's LDS reads are done
+#pragma unroll
+        for (int m = 0; m < E; ++m) lds[grp * region + lay(j + Tc * m, c)] = fw[0][m];
+        __syncthreads();
+        // 2. contraction for this group's components
+        cplx<T> acc[OPG][E];
+#pragma unroll
+        for (int k = 0; k < OPG; ++k)
+#pragma unroll
+            for (int m = 0; m < E; ++m) acc[k][m] = {T(0), T(0)};
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch)
+#pragma unroll
+            for (int m = 0; m < E; ++m) {
+                const cplx<T> r = lds[ch * region + lay(j + Tc * m, c)];
+#pragma unroll
+                for (int k = 0; k < OPG; ++k) {
+                    acc[k][m].x -= sv[k][ch][m] * r.y;
+                    acc[k][m].y += sv[k][ch][m] * r.x;
+                }
+            }
+        if (b + 1 < g.B) {
+            const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_g + (b + 1) * in_real, plane_bytes);
+#pragma unroll
+            for (int m = 0; m < EH; ++m) fw[0][m] = buf_cplx<T>(rr, r_lane, m * r_step);
+        }
+        // inverse transforms (their first stage's barrier precedes any LDS write)
+        fft_regs_k<T, N, E, false, false, OPG>(acc, twr, lds + OPG * grp * region, region, lay, c, j);
+        if (valid && has_v) {
+#pragma unroll
+            for (int k = 0; k < OPG; ++k) {
+                cplx<T>* dst = out_b + (int64_t)(b * 6 + OPG * grp + k) * g.oqs;
+#pragma unroll
+                for (int m = 0; m < EH; ++m) {
+                    const int z = j + Tc * m;
+                    if (z < g.nz) dst[z * ors] = acc[k][m];
+                }
+            }
+        }
+    }
+}
+
+
+template <typename T, int L, int E, int NC, bool GROUPED>
+static void z_launch(int64_t blocks, int tk, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+                     const cplx<T>* tw, hipStream_t s) {
+    const int groups = GROUPED ? NC : 1;
+    size_t lds = z_lds_bytes(L, tk, NC, groups, (int)sizeof(T));
+    const int ld = z_lds_ld(tk, (int)sizeof(T));
+    const dim3 block(groups * tk * (L / E));
+    if constexpr (GROUPED) {
+        hipLaunchKernelGGL((k_z_grouped<T, L, E, NC>), dim3((unsigned)blocks), block, lds, s, in, out, spec, g, tw, tk,
+                           ld);
+    } else if constexpr (L >= 2 && L <= 256) {
+        if (z_stage_spec(L, tk, NC, g.nkz_s, g.B, (int)sizeof(T))) {
+            lds += z_stage_bytes(tk, NC, g.nkz_s, (int)sizeof(T));
+            const dim3 grid((unsigned)blocks);
+            if (tk == 4)
+                hipLaunchKernelGGL((k_z_serial<T, L, E, NC, 4>), grid, block, lds, s, in, out, spec, g, tw, tk, ld);
+            else if (tk == 8)
+                hipLaunchKernelGGL((k_z_serial<T, L, E, NC, 8>), grid, block, lds, s, in, out, spec, g, tw, tk, ld);
+            else
+                hipLaunchKernelGGL((k_z_serial<T, L, E, NC, 16>), grid, block, lds, s, in, out, spec, g, tw, tk, ld);
+        } else {
+            hipLaunchKernelGGL((k_z_serial<T, L, E, NC, 0>), dim3((unsigned)blocks), block, lds, s, in, out, spec, g,
+                               tw, tk, ld);
+        }
+    } else {
+        hipLaunchKernelGGL((k_z_serial<T, L, E, NC, 0>), dim3((unsigned)blocks), block, lds, s, in, out, spec, g, tw,
+                           tk, ld);
+    }
+}
+
+template <typename T, int EV, int NC, bool GROUPED>
+static void z_ev(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g, const cplx<T>* tw,
+                 int tk, int64_t blocks, hipStream_t s) {
+    switch (N) {
+#define Z_CASE(L, EVV)                                                                                     \
+    case L: z_launch<T, L, (L < EVV ? L : EVV), NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
+        DDS_FOR_LENGTHS(Z_CASE, EV)
+#undef Z_CASE
+        default: fail(DDSTRESS_E_UNSUPPORTED, "z transform length not supported");
+    }
+}
+
+// Larger element classes, instantiated for the long z lengths only.
+template <typename T, int EV, int NC, bool GROUPED>
+static void z_ev_long(int N, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g, const cplx<T>* tw,
+                      int tk, int64_t blocks, hipStream_t s) {
+    switch (N) {
+        case 256: z_launch<T, 256, EV, NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
+        case 512: z_launch<T, 512, EV, NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
+        case 1024: z_launch<T, 1024, EV, NC, GROUPED>(blocks, tk, in, out, spec, g, tw, s); break;
+        default: fail(DDSTRESS_E_UNSUPPORTED, "z transform length not supported");
+    }
+}
+
+template <typename T, int NC, bool GROUPED>
+void z_dispatch(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+                       const cplx<T>* tw, int tk, int64_t blocks, hipStream_t s) {
+    constexpr int EV = sizeof(T) == 4 ? 4 : 2;
+    if (ev == EV) z_ev<T, EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
+    else if (ev == 2 * EV) z_ev_long<T, 2 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
+    else if (ev == 4 * EV) z_ev_long<T, 4 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
+    else if constexpr (8 * EV <= 16) {
+        if (ev == 8 * EV) z_ev_long<T, 8 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
+        else fail(DDSTRESS_E_INVALID, "z element class not supported");
+    } else {
+        fail(DDSTRESS_E_INVALID, "z element class not supported");
+    }
+}
+
+
+#define DDS_Z_INSTANTIATE(T, GROUPED)                                                                      \
+    template void z_dispatch<T, 3, GROUPED>(int, int, const cplx<T>*, cplx<T>*, const T*, const ZGeom&,     \
+                                            const cplx<T>*, int, int64_t, hipStream_t);                    \
+    template void z_dispatch<T, 6, GROUPED>(int, int, const cplx<T>*, cplx<T>*, const T*, const ZGeom&,     \
+                                            const cplx<T>*, int, int64_t, hipStream_t);                    \
+    template void z_dispatch<T, 9, GROUPED>(int, int, const cplx<T>*, cplx<T>*, const T*, const ZGeom&,     \
+                                            const cplx<T>*, int, int64_t, hipStream_t);
+
+}  // namespace dds

@@ -21,6 +21,15 @@ def cache_path():
 LAYOUT = "z2"
 
 
+def device_tag():
+    """Architecture and compute-unit count of the current device (the marketing
+    name can read differently under a profiler)."""
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(p, "gcnArchName", "") or p.name
+    return f"{arch.split(':')[0]}-{p.multi_processor_count}cu"
+
+
 def shape_key(desc, device_name=""):
     n = "x".join(str(v) for v in desc.n)
     return f"{device_name}|{n}|fp{desc.precision}|C{3 * desc.n_lines}|B{desc.batch}|{LAYOUT}"
@@ -61,7 +70,7 @@ def get_tuning(desc, stream=None, path=None, refresh=False):
     """The cached tuning for this shape, running the autotuner on a miss."""
     import torch
     path = path or cache_path()
-    key = shape_key(desc, torch.cuda.get_device_name())
+    key = shape_key(desc, device_tag())
     data = _read(path)
     if not refresh and key in data:
         return from_dict(data[key])

@@ -1,0 +1,60 @@
+"""Host-side checks of the rocprofv3 summaries: launch selection, copy-kernel
+calibration and the source digest that ties a traffic report to the kernels
+it measured. Synthetic counter files, no GPU."""
+import csv
+import json
+import os
+
+from paper_1804_01830_amd import profiling as P
+
+FIELDS = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id", "Grid_Size",
+          "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size", "VGPR_Count",
+          "Accum_VGPR_Count", "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+
+LINE = {"metric": "m", "config": {"grid": [128, 128, 32], "workload": "disk-mixed-128x128x32", "batch": 8},
+        "plan_info": {"padded": [256, 256, 64], "tile_z": 8, "ez": 4, "z_groups": 1},
+        "roofline": {"kernel": "k_z_serial", "algorithmic_bytes_per_launch": 1000000}}
+BLOCK = 8 * 16                                    # tk * Pz / E threads
+GRID = ((129 + 7) // 8) * 256 * BLOCK             # kx tiles x ky rows blocks
+
+
+def _write(directory, counter, rows):
+    os.makedirs(directory)
+    with open(os.path.join(directory, "run_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=FIELDS)
+        w.writeheader()
+        for i, (name, wg, grid, val) in enumerate(rows):
+            w.writerow({k: 0 for k in FIELDS} | {"Dispatch_Id": i, "Kernel_Name": name, "Workgroup_Size": wg,
+                                                  "Grid_Size": grid, "Counter_Name": counter,
+                                                  "Counter_Value": val})
+
+
+def test_traffic_uses_matching_launches_and_copy_scale(tmp_path):
+    z = "void dds::k_z_serial<float, 64, 4, 3>(dds::cplx<float> const*)"
+    # tuning launches of another shape, three timed launches, the 512 MiB copy
+    _write(tmp_path / "f", "FETCH_SIZE", [(z, 256, GRID * 2, 9e9), (z, BLOCK, GRID, 400.0), (z, BLOCK, GRID, 410.0),
+                                          (z, BLOCK, GRID, 405.0), ("elementwise_kernel", 256, 1 << 20, 262144.0)])
+    _write(tmp_path / "w", "WRITE_SIZE", [(z, BLOCK, GRID, 600.0), ("elementwise_kernel", 256, 1 << 20, 524288.0)])
+    t = P.traffic(str(tmp_path / "f"), str(tmp_path / "w"), LINE, 512)
+    assert t["FETCH_SIZE"]["launches"] == 3 and abs(t["FETCH_SIZE"]["factor"] - 2.0) < 1e-12
+    assert t["FETCH_SIZE"]["bytes"] == 405.0 * 1024 * 2.0
+    assert t["WRITE_SIZE"]["bytes"] == 600.0 * 1024 * 1.0
+
+
+def test_stored_traffic_requires_current_sources(tmp_path):
+    _write(tmp_path / "f", "FETCH_SIZE", [("void dds::k_z_serial<float>", BLOCK, GRID, 100.0),
+                                          ("copy", 64, 64, 1024.0)])
+    _write(tmp_path / "w", "WRITE_SIZE", [("void dds::k_z_serial<float>", BLOCK, GRID, 50.0),
+                                          ("copy", 64, 64, 1024.0)])
+    line_file = tmp_path / "bench.log"
+    line_file.write_text("[bench] noise\n" + json.dumps(LINE) + "\n")
+    report = P.traffic_report(str(tmp_path / "f"), str(tmp_path / "w"), str(line_file), 1, "t",
+                              "rocprofv3 --pmc {COUNTER} -- python3 bench.py")
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "z.md").write_text(report)
+    got = P.stored_traffic(str(prof), "disk-mixed-128x128x32", 8, "k_z_serial")
+    assert got == (100.0 + 50.0) * 1024
+    assert P.stored_traffic(str(prof), "disk-mixed-128x128x32", 1, "k_z_serial") is None
+    (prof / "z.md").write_text(report.replace(P.source_digest(), "0" * 64))
+    assert P.stored_traffic(str(prof), "disk-mixed-128x128x32", 8, "k_z_serial") is None
