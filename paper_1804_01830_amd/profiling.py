@@ -28,7 +28,9 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEVICE_SOURCES = ("csrc/passes.hip", "csrc/fft_device.hpp", "csrc/ddstress_internal.hpp")
+DEVICE_SOURCES = ("csrc/passes.hip", "csrc/zfused.hpp", "csrc/z_serial_f32.hip", "csrc/z_serial_f64.hip",
+                  "csrc/z_grouped_f32.hip", "csrc/z_grouped_f64.hip", "csrc/fft_device.hpp",
+                  "csrc/ddstress_internal.hpp")
 
 
 def source_digest():
