@@ -106,6 +106,28 @@ def time_path(plan, rho, out, steps, warmup, profile, graph=False):
     return wall, per, passes, calls
 
 
+def time_host_io(plan, rho, steps, warmup):
+    """Host-to-host steps: density from pinned host memory, stress back to
+    pinned host memory (PCIe both ways), one synchronisation per step."""
+    import torch
+    from paper_1804_01830_amd import binding as Bd
+    rho_h = rho.cpu().pin_memory()
+    out_h = torch.empty(tuple(plan.new_output().shape), dtype=rho.dtype).pin_memory()
+    for _ in range(warmup):
+        plan.set_density(rho_h, Bd.HOST)
+        plan.stress(out_h, where=Bd.HOST)
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(steps):
+        t = time.perf_counter()
+        plan.set_density(rho_h, Bd.HOST)
+        plan.stress(out_h, where=Bd.HOST)
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - t)
+    per.sort()
+    return sum(per), per, rho_h.numel() * rho_h.element_size() + out_h.numel() * out_h.element_size()
+
+
 def pct(sorted_vals, q):
     k = min(len(sorted_vals) - 1, max(0, int(round(q / 100.0 * (len(sorted_vals) - 1)))))
     return sorted_vals[k]
@@ -289,13 +311,15 @@ def main():
         out = plan.new_output()
         steps = args.steps if prec == 32 else (args.fp64_steps or max(10, args.steps // 2))
         wall, per, passes, calls = time_path(plan, rho, out, steps, args.warmup, profile=True)
-        graph = None
+        graph = host = None
         if prec == 32:
             gw, gper, _, _ = time_path(plan, rho, out, steps, args.warmup, profile=False, graph=True)
             graph = dict(wall=gw, per=gper)
+            hw, hper, hbytes = time_host_io(plan, rho, min(steps, 50), min(args.warmup, 5))
+            host = dict(wall=hw, per=hper, bytes=hbytes, steps=min(steps, 50))
         info = plan.info()
         res[prec] = dict(plan=plan, info=info, wall=wall, per=per, passes=passes, calls=calls, steps=steps,
-                         plan_s=plan_s, graph=graph, tune=Tn.to_dict(tune) if tune is not None else None,
+                         plan_s=plan_s, graph=graph, host=host, tune=Tn.to_dict(tune) if tune is not None else None,
                          out=out[0].double().cpu().numpy() if (B == 1 or plain_one) else None,
                          cells=Bp * nx * ny * nz)
         print(f"[bench] precision {prec}: {wall / steps * 1e3:.4f} ms/step, plan {plan_s:.2f} s, "
@@ -349,6 +373,12 @@ def main():
         "tuning": r32["tune"],
         "pass_ms": {k: round(v / max(r32["calls"], 1), 5) for k, v in r32["passes"].items()},
         "path_algorithmic_gbs": round(pbytes / (ms32 * 1e-3) / 1e9, 1),
+        "path_frac": round(pbytes / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "host_to_host": {"value": round(cells / (r32["host"]["wall"] / r32["host"]["steps"]), 1),
+                         "ms_per_step": round(r32["host"]["wall"] / r32["host"]["steps"] * 1e3, 5),
+                         "p50_ms": round(pct(r32["host"]["per"], 50) * 1e3, 5),
+                         "pcie_bytes_per_step": r32["host"]["bytes"],
+                         "note": "density from and stress to pinned host memory; not the headline value"},
         "plan_build_s": {"fp32": round(r32["plan_s"], 3), "fp64": round(r64["plan_s"], 3)},
         "roofline": roofline,
         "plan_info": plan_info,

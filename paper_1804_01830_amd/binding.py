@@ -161,14 +161,19 @@ class Plan:
         return self._h
 
     def set_density(self, rho, where=DEVICE_BORROW, stream=None):
-        self._check_tensor(rho, (self.batch, self.channels))
+        """Hand the density to the plan: a CUDA tensor borrowed (DEVICE_BORROW)
+        or copied (DEVICE_COPY), or a CPU tensor copied from host memory (HOST;
+        pinned memory makes the copy asynchronous)."""
+        self._check_tensor(rho, (self.batch, self.channels), host=(where == HOST))
         self._rho_ref = rho           # keeps a borrowed buffer alive
         check(load().ddstress_set_density(self._h, ctypes.c_void_p(rho.data_ptr()), where,
                                           _stream_handle(stream)))
 
-    def stress(self, sigma, stream=None):
-        self._check_tensor(sigma, (self.batch, 6))
-        check(load().ddstress_stress(self._h, ctypes.c_void_p(sigma.data_ptr()), DEVICE_BORROW,
+    def stress(self, sigma, stream=None, where=DEVICE_BORROW):
+        """Evaluate into ``sigma``: a CUDA tensor, or a CPU tensor with
+        where=HOST (copied back on the stream; synchronise before reading)."""
+        self._check_tensor(sigma, (self.batch, 6), host=(where == HOST))
+        check(load().ddstress_stress(self._h, ctypes.c_void_p(sigma.data_ptr()), where,
                                      _stream_handle(stream)))
         return sigma
 
@@ -197,12 +202,14 @@ class Plan:
         nx, ny, nz = self.n
         return torch.empty((self.batch, 6, nz, ny, nx), dtype=dt, device="cuda")
 
-    def _check_tensor(self, t, lead):
+    def _check_tensor(self, t, lead, host=False):
         import torch
         dt = torch.float32 if self.precision == 32 else torch.float64
         nx, ny, nz = self.n
-        if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or tuple(t.shape) != (*lead, nz, ny, nx):
-            raise ValueError(f"expected a contiguous CUDA {dt} tensor of shape {(*lead, nz, ny, nx)}, "
+        where = "CPU" if host else "CUDA"
+        if (t.is_cuda == host or t.dtype != dt or not t.is_contiguous()
+                or tuple(t.shape) != (*lead, nz, ny, nx)):
+            raise ValueError(f"expected a contiguous {where} {dt} tensor of shape {(*lead, nz, ny, nx)}, "
                              f"got {tuple(t.shape)} {t.dtype} on {t.device}")
 
     def set_profiling(self, enable=True):

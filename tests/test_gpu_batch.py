@@ -77,3 +77,31 @@ def test_batch_bounds_are_checked():
         plan.stress_batch(rho, out, 3)
     assert e.value.status == B.E_INVALID
     plan.close()
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_host_buffers_give_device_bits(precision):
+    """Density from host memory and stress back to host memory (pinned CPU
+    tensors) give the same bits as device buffers; DEVICE_COPY as well."""
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w = W.random_field((20, 12, 6), n_lines=1, batch=2, seed=17)
+    dt = torch.float32 if precision == 32 else torch.float64
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision, batch=2)
+    plan = B.Plan(desc)
+    rho_h = torch.from_numpy(w["rho"]).to(dt).contiguous().pin_memory()
+    rho_d = rho_h.to("cuda")
+    ref = plan.new_output()
+    plan.set_density(rho_d)
+    plan.stress(ref)
+    out_h = torch.empty(tuple(ref.shape), dtype=dt).pin_memory()
+    plan.set_density(rho_h, where=B.HOST)
+    plan.stress(out_h, where=B.HOST)
+    copy = plan.new_output()
+    plan.set_density(rho_d, where=B.DEVICE_COPY)
+    plan.stress(copy)
+    torch.cuda.synchronize()
+    assert torch.equal(out_h, ref.cpu()) and torch.equal(copy, ref)
+    with pytest.raises(ValueError):
+        plan.stress(out_h)                    # a CPU tensor needs where=HOST
+    plan.close()
