@@ -29,7 +29,7 @@ namespace dds {
 // column than the grouped form: better for few realisations.
 // ----------------------------------------------------------------------------
 template <typename T, int N, int E, int NC, int TK>
-__global__ void __launch_bounds__(512) k_z_serial(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0 && NC == 3 ? 3 : 1))) k_z_serial(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
                                                   const T* __restrict__ spec, ZGeom g,
                                                   const cplx<T>* __restrict__ tw, int tk_arg, int ld_arg) {
     constexpr int Tc = N / E;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(512) k_z_serial(const cplx<T>* __restrict__ in
     }
 
     T sv[6][E];
-    DDS_LOAD_SPEC(sv, 0)
+    if constexpr (!SL) DDS_LOAD_SPEC(sv, 0)
     for (int b = 0; b < g.B; ++b) {
         cplx<T> acc[6][1][E];
 #pragma unroll
@@ -158,6 +158,10 @@ __global__ void __launch_bounds__(512) k_z_serial(const cplx<T>* __restrict__ in
                 const bool more = gq < 2 || l + 1 < NC / 3;
                 if (more) DDS_LOAD_RHO(nxt, b, ch + 1)
                 fft_regs_k<T, N, E, true, HZ, 1>(cur, twr, lds, 0, lay, c, j);
+                // staged values are read from LDS here, after the transform (they
+                // need no registers while it runs); values from memory were
+                // requested before it
+                if constexpr (SL) DDS_LOAD_SPEC(sv, ch)
 #pragma unroll
                 for (int v = 0; v < 6; ++v) {
                     // signs of mirrored spectrum rows (wave-uniform); staged
@@ -174,7 +178,7 @@ __global__ void __launch_bounds__(512) k_z_serial(const cplx<T>* __restrict__ in
                     }
                 }
                 if (more) {
-                    DDS_LOAD_SPEC(sv, ch + 1)
+                    if constexpr (!SL) DDS_LOAD_SPEC(sv, ch + 1)
 #pragma unroll
                     for (int m = 0; m < EH; ++m) cur[0][m] = nxt[0][m];
                 }
@@ -182,7 +186,7 @@ __global__ void __launch_bounds__(512) k_z_serial(const cplx<T>* __restrict__ in
         }
         if (b + 1 < g.B) {      // first channel of the next realisation
             DDS_LOAD_RHO(cur, b + 1, 0)
-            DDS_LOAD_SPEC(sv, 0)
+            if constexpr (!SL) DDS_LOAD_SPEC(sv, 0)
         }
 #undef DDS_LOAD_RHO
 #undef DDS_LOAD_SPEC
