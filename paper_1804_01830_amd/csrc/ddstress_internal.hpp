@@ -78,6 +78,10 @@ void launch_z_fused(int N, int ev, int groups, const cplx<T>* in, cplx<T>* out, 
 
 // Launch geometry: threads per block, element classes and defaults.
 int x_threads(int M, int rows, int ev);
+struct XLayout {
+    int ld, s;       // LDS row stride and pad shift of the x passes
+};
+XLayout x_lds_layout(int M, int E, int elem_bytes);
 int x_lds_ld(int M, int E, int elem_bytes);
 int col_threads(int N, int tk, int ev);
 int z_threads(int N, int groups, int tk, int ev);

@@ -209,6 +209,10 @@ struct RowMajor {      // element i of row r at r*ld + i
     int ld;
     __device__ __forceinline__ int operator()(int i, int r) const { return r * ld + i; }
 };
+struct RowPad {        // element i of row r at r*ld + i + (i >> s): one pad element every 2^s
+    int ld, s;
+    __device__ __forceinline__ int operator()(int i, int r) const { return r * ld + i + (i >> s); }
+};
 
 // One radix-R Stockham stage. Butterfly b = j + Tc*q (q < E/R) reads
 // x[b + r N/R], multiplies by exp(-/+ 2 pi i (b mod Ns) r / (Ns R)), applies

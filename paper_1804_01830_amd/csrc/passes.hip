@@ -12,6 +12,13 @@
 // interaction coefficients when a plan is built.
 #include "ddstress_internal.hpp"
 
+#include <functional>
+#include <map>
+#include <mutex>
+#include <set>
+#include <tuple>
+#include <vector>
+
 namespace dds {
 
 
@@ -25,7 +32,7 @@ template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_x_r2c(const T* __restrict__ in, cplx<T>* __restrict__ out,
                                                int64_t nrows, int n_in, int64_t in_stride,
                                                int64_t out_stride, const cplx<T>* __restrict__ tw,
-                                               int rows_per_block, int pairs, int ld) {
+                                               int rows_per_block, int pairs, int ld, int lsh) {
     constexpr int Tc = M / E;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -33,7 +40,7 @@ __global__ void __launch_bounds__(512) k_x_r2c(const T* __restrict__ in, cplx<T>
     const int rl = threadIdx.x / Tc;
     const int64_t row = (int64_t)blockIdx.x * rows_per_block + rl;
     const bool valid = row < nrows;
-    const RowMajor lay{ld};
+    const RowPad lay{ld, lsh};
     const T* src = in + (valid ? row : 0) * in_stride;
     cplx<T> reg[E];
     if (pairs) {        // rows aligned to a pair of reals and n_in even: one access per pair
@@ -87,7 +94,7 @@ template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
                                                int64_t nrows, int n_out, int64_t in_stride,
                                                int64_t out_stride, const cplx<T>* __restrict__ tw,
-                                               int rows_per_block, int pairs, int ld) {
+                                               int rows_per_block, int pairs, int ld, int lsh) {
     constexpr int Tc = M / E;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -95,7 +102,7 @@ __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T
     const int rl = threadIdx.x / Tc;
     const int64_t row = (int64_t)blockIdx.x * rows_per_block + rl;
     const bool valid = row < nrows;
-    const RowMajor lay{ld};
+    const RowPad lay{ld, lsh};
     const cplx<T>* src = in + (valid ? row : 0) * in_stride;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -278,19 +285,94 @@ int default_z_tk(int N, int C, int groups, int elem_bytes) {
 }
 
 
-// LDS row stride of the x passes: at least M + 1 elements and, when a wave
-// spans several rows, congruent to the threads per row modulo the elements of
-// one 256-byte bank window, so that the rows a wave touches fall on disjoint
-// banks.
-int x_lds_ld(int M, int E, int elem_bytes) {
-    const int es = 2 * elem_bytes;
-    const int win = 256 / es;
-    const int tc = M / E;
-    int ld = M + 1;
-    if (tc * es >= 256) return ld;
-    while (ld % win != tc % win) ++ld;
-    return ld;
+// LDS layout of the x passes: element i of row r at r * ld + i + (i >> s),
+// one pad element every 2^s. The layout is chosen per (M, E, precision) by
+// evaluating an LDS bank model over a few candidates: 32 banks of 4 bytes, an
+// access of w bytes per lane served 128 / w lanes at a time, each group taking
+// as many cycles as the most distinct dwords on one bank. (The model
+// reproduces the bank-conflict counters measured on the passes' kernels.) The
+// accesses modelled are one block's Stockham exchanges (the same index
+// formulas as fft_stage), the row split reads of k and M - k and of element M.
+namespace {
+
+int lds_group_cycles(const std::vector<int>& addr, int width) {
+    const int per = std::max(1, 128 / width);
+    int cycles = 0;
+    for (size_t g0 = 0; g0 < addr.size(); g0 += per) {
+        std::map<int, std::set<int>> banks;
+        for (size_t l = g0; l < std::min(addr.size(), g0 + per); ++l)
+            for (int d = 0; d < width / 4; ++d) {
+                const int dw = addr[l] / 4 + d;
+                banks[dw % 32].insert(dw);
+            }
+        size_t worst = 0;
+        for (auto& kv : banks) worst = std::max(worst, kv.second.size());
+        cycles += (int)worst;
+    }
+    return cycles;
 }
+
+double x_layout_cost(int M, int E, int elem, int ld, int s) {
+    const int Tc = M / E, width = 2 * elem;
+    const int nthr = std::min(256, std::max(64, Tc));
+    auto lay = [&](int i, int r) { return (r * ld + i + (i >> s)) * width; };
+    std::vector<std::function<int(int, int)>> acc;
+    for (int Ns = 1; Ns < M;) {
+        const int R = std::min(std::min(8, E), M / Ns), NB = E / R;
+        const bool first = Ns == 1, last = Ns * R == M;
+        for (int q = 0; q < NB; ++q)
+            for (int r = 0; r < R; ++r) {
+                if (!first) acc.push_back([=](int j, int row) { return lay(j + Tc * q + r * (M / R), row); });
+                if (!last)
+                    acc.push_back([=](int j, int row) {
+                        const int b = j + Tc * q;
+                        return lay((b / Ns) * Ns * R + (b % Ns) + r * Ns, row);
+                    });
+            }
+        Ns *= R;
+    }
+    for (int m = 0; m < E; ++m) {
+        acc.push_back([=](int j, int row) { return lay(j + Tc * m, row); });
+        acc.push_back([=](int j, int row) { return lay((M - (j + Tc * m)) & (M - 1), row); });
+    }
+    long cycles = 0, ideal = 0;
+    std::vector<int> addr;
+    for (int w0 = 0; w0 < nthr; w0 += 64)
+        for (auto& f : acc) {
+            addr.clear();
+            for (int t = w0; t < std::min(nthr, w0 + 64); ++t) addr.push_back(f(t % Tc, t / Tc));
+            cycles += lds_group_cycles(addr, width);
+            ideal += ((int)addr.size() * width + 127) / 128;
+        }
+    return (double)cycles / (double)std::max(1L, ideal);
+}
+
+}  // namespace
+
+XLayout x_lds_layout(int M, int E, int elem_bytes) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, XLayout> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(M, E, elem_bytes);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    XLayout best{M + 1, 30};
+    if (M >= 8) {
+        double best_cost = x_layout_cost(M, E, elem_bytes, M + 1, 30);
+        for (int s : {3, 4})
+            for (int extra = 0; extra < 16; ++extra) {
+                const int ld = M + (M >> s) + 1 + extra;
+                const double c = x_layout_cost(M, E, elem_bytes, ld, s);
+                if (c < best_cost - 1e-9) {
+                    best_cost = c;
+                    best = {ld, s};
+                }
+            }
+    }
+    cache[key] = best;
+    return best;
+}
+int x_lds_ld(int M, int E, int elem_bytes) { return x_lds_layout(M, E, elem_bytes).ld; }
 
 // Real rows can be accessed in pairs when every row starts on a pair boundary.
 template <typename T>
@@ -307,10 +389,10 @@ static void x_r2c_ev(int M, const T* in, cplx<T>* out, int64_t nrows, int n_in, 
 #define X_CASE(L, EVV)                                                                                     \
     case L: {                                                                                              \
         constexpr int E = L < EVV ? L : EVV;                                                               \
-        const int ld = x_lds_ld(L, E, (int)sizeof(T));                                                     \
-        const size_t lds = (size_t)rows * ld * sizeof(cplx<T>);                                            \
+        const XLayout xl = x_lds_layout(L, E, (int)sizeof(T));                                            \
+        const size_t lds = (size_t)rows * xl.ld * sizeof(cplx<T>);                                         \
         hipLaunchKernelGGL((k_x_r2c<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, in, out, \
-                           nrows, n_in, in_stride, out_stride, tw, rows, pairs, ld);                           \
+                           nrows, n_in, in_stride, out_stride, tw, rows, pairs, xl.ld, xl.s);                           \
         break;                                                                                             \
     }
         DDS_FOR_LENGTHS(X_CASE, EV)
@@ -328,10 +410,10 @@ static void x_c2r_ev(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out,
 #define X_CASE(L, EVV)                                                                                     \
     case L: {                                                                                              \
         constexpr int E = L < EVV ? L : EVV;                                                               \
-        const int ld = x_lds_ld(L, E, (int)sizeof(T));                                                     \
-        const size_t lds = (size_t)rows * ld * sizeof(cplx<T>);                                            \
+        const XLayout xl = x_lds_layout(L, E, (int)sizeof(T));                                            \
+        const size_t lds = (size_t)rows * xl.ld * sizeof(cplx<T>);                                         \
         hipLaunchKernelGGL((k_x_c2r<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, in, out, \
-                           nrows, n_out, in_stride, out_stride, tw, rows, pairs, ld);                          \
+                           nrows, n_out, in_stride, out_stride, tw, rows, pairs, xl.ld, xl.s);                          \
         break;                                                                                             \
     }
         DDS_FOR_LENGTHS(X_CASE, EV)
