@@ -148,7 +148,7 @@ Shape make_shape(const ddstress_desc* d) {
     s.C = 3 * d->n_lines;
     s.B = d->batch;
     s.elem = d->precision == 32 ? 4 : 8;
-    s.zg = default_z_groups(s.C, s.B);
+    s.zg = default_z_groups(s.P[2], s.C, s.B, s.elem);
     s.tkz = default_z_tk(s.P[2], s.C, s.zg, s.elem);
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
     set_mirrors(s, predict_mirror(d, 1), predict_mirror(d, 2));

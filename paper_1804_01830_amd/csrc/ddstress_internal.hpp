@@ -95,7 +95,7 @@ int default_z_tk(int N, int C, int groups, int elem_bytes);
 size_t z_lds_bytes(int N, int tk, int C, int groups, int elem_bytes);
 int z_lds_ld(int tk, int elem_bytes);
 bool z_groups_ok(int groups, int C);
-int default_z_groups(int C, int B);
+int default_z_groups(int N, int C, int B, int elem_bytes);
 int z_max_threads(int groups);
 size_t z_stage_bytes(int tk, int C, int nkz, int elem_bytes);
 bool z_stage_spec(int N, int tk, int C, int nkz, int B, int elem_bytes);

@@ -199,8 +199,16 @@ int col_threads(int N, int tk, int ev) { return tk * (N / ecount(N, ev)); }
 int z_threads(int N, int groups, int tk, int ev) { return groups * tk * (N / ecount(N, ev)); }
 int z_max_threads(int groups) { return groups == 1 ? 512 : 768; }
 bool z_groups_ok(int groups, int C) { return groups == 1 || groups == C; }
-// Many realisations amortise the grouped form's larger blocks.
-int default_z_groups(int C, int B) { return B >= 16 ? C : 1; }
+// Many realisations amortise the grouped form's larger blocks; it is the
+// default from 16 realisations on, where one column per group fits a block
+// (threads and LDS).
+int default_z_groups(int N, int C, int B, int elem_bytes) {
+    if (B < 16) return 1;
+    const int ev = default_ev_z(N, C, elem_bytes);
+    const int e = N < ev ? N : ev;
+    const bool fits = z_threads(N, C, 1, e) <= z_max_threads(C) && z_lds_bytes(N, 1, C, C, elem_bytes) <= 64 * 1024;
+    return fits ? C : 1;
+}
 
 // LDS column stride of the fused z kernels (one column block per tile).
 int z_lds_ld(int tk, int elem_bytes) {

@@ -36,6 +36,10 @@ CASES = {
     "rand-1x1x1": lambda: W.random_field((1, 1, 1), n_lines=1, seed=4),
     "rand-1x6x2": lambda: W.random_field((1, 6, 2), n_lines=1, seed=5, d=(1.0, 1.0, 2.0)),
     "rand-40x1x12-diag": lambda: W.random_field((40, 1, 12), seed=6, d=(1.0, 1.0, 1.0), lines=[DIAG]),
+    # the longest supported axes (512 cells: transforms of length 1024)
+    "rand-512x2x2-max-x": lambda: W.random_field((512, 2, 2), n_lines=1, seed=11),
+    "rand-2x512x2-max-y": lambda: W.random_field((2, 512, 2), n_lines=1, seed=11),
+    "rand-2x2x512-max-z-L3": lambda: W.random_field((2, 2, 512), n_lines=3, seed=11),
 }
 
 
@@ -197,3 +201,43 @@ def test_mirror_compressed_spectrum_matches_full(lines, mir):
     (a, ca), (b, cb) = outs
     assert np.linalg.norm(a - b) <= 1e-14 * np.linalg.norm(b)
     assert ca <= cb
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("lines", [1, 2, 3])
+def test_grouped_long_z_classes(precision, lines):
+    """The grouped fused z form on a 1024-point z transform takes the larger
+    element classes (8 per thread with six channels). Forced through the
+    tuning struct it agrees with the direct sum where its block fits (FP32, up
+    to six channels); elsewhere (LDS > 64 KiB) the plan is refused, and a
+    default plan with many realisations falls back to the single-group form."""
+    from paper_1804_01830_amd import binding as B
+    import torch
+    w = W.random_field((3, 2, 300), n_lines=lines, seed=12)
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision)
+    d = B.Plan(desc).info()
+    t = B.Tuning()
+    t.rows_x, t.tk_y, t.tk_z, t.ex, t.ey = d.rows_x, d.tile_y, 1, d.ex, d.ey
+    t.z_groups = d.channels
+    fits = precision == 32 and lines <= 2
+    if not fits:
+        with pytest.raises(B.DDStressError) as e:
+            B.Plan(desc, tuning=t)
+        assert e.value.status == B.E_INVALID
+        many = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision, batch=16)
+        assert B.Plan(many).info().z_groups == 1
+        return
+    ref = stress_direct(w["rho"][0], w["d"], w["lines"], w["mu"], w["nu"])[None]
+    plan = B.Plan(desc, tuning=t)
+    info = plan.info()
+    assert info.z_groups == d.channels and info.padded[2] == 1024
+    _say(f"[grouped-long] precision={precision} C={d.channels} ez={info.ez}")
+    dt = torch.float32 if precision == 32 else torch.float64
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=dt)
+    out = plan.new_output()
+    plan.set_density(rho)
+    plan.stress(out)
+    torch.cuda.synchronize()
+    comp, whole = rel_l2(out.double().cpu().numpy(), ref)
+    assert np.all(comp <= TOL[precision]) and whole <= TOL[precision]
+    plan.close()
