@@ -195,6 +195,7 @@ struct ddstress_plan_s {
     bool have_density = false;
     int rows_x = 1, tk_y = 1;      // x rows and y columns per block
     int ex = 16, ey = 16, ez = 8;  // element classes of the x, y and fused z passes
+    bool yx = false;               // inverse y and x as one kernel
     double re_max = 0.0, im_max = 0.0;
     // per-pass event timing: events are pooled and reused between folds
     bool profiling = false;
@@ -421,6 +422,14 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     gi.ips = (int64_t)Py * s.wx;
     gi.ors = s.wx;
     gi.ops = (int64_t)Ny * s.wx;
+    if constexpr (sizeof(T) == 4) {
+        if (p->yx) {        // one kernel; the x pass's time shows as zero
+            launch_yx_inv(w1, sigma, B6 * Nz, Py, s.M, Ny, Nx, s.wx, tw, st);
+            p->mark(st);
+            p->mark(st);
+            return;
+        }
+    }
     launch_col_fft<T>(Py, p->ey, false, w1, w2, gi, tw, p->tk_y, st);
     p->mark(st);
     // x inverse: rows (b, v, z, y) -> Nx reals
@@ -493,11 +502,14 @@ bool z_ok(const Shape& s, int tk, int ev, int groups) {
 
 struct LaunchChoice {
     int rows_x, ex, tk_y, ey, ez, zg;
+    bool yx;
 };
+
+bool yx_ok(const Shape& s) { return yx_inv_fits(s.P[1], s.M, s.N[1], s.elem); }
 
 LaunchChoice default_launch(const Shape& s) {
     return {default_rows(s.M, s.elem), default_ev_col(s.M), default_col_tk(s.P[1], s.elem), default_ev_col(s.P[1]),
-            default_ev_z(s.P[2], s.zg, s.elem), s.zg};
+            default_ev_z(s.P[2], s.zg, s.elem), s.zg, yx_ok(s)};
 }
 
 // Apply a tuning (zero element classes select the defaults) after checking it.
@@ -509,7 +521,9 @@ LaunchChoice apply_tuning(Shape& s, const ddstress_tuning* t) {
     const int ez = t->ez ? t->ez : default_ev_z(s.P[2], zg, s.elem);
     if (!rows_ok(s, t->rows_x, ex) || !col_ok(s, s.P[1], t->tk_y, ey) || !z_ok(s, t->tk_z, ez, zg))
         fail(DDSTRESS_E_INVALID, "tuning choice outside the launch limits of this shape");
-    c = {t->rows_x, ex, t->tk_y, ey, ez, zg};
+    if (t->yx < 0 || t->yx > 2 || (t->yx == 2 && !yx_ok(s)))
+        fail(DDSTRESS_E_INVALID, "fused inverse y-x does not apply to this shape");
+    c = {t->rows_x, ex, t->tk_y, ey, ez, zg, t->yx == 0 ? yx_ok(s) : t->yx == 2};
     s.zg = zg;
     s.tkz = t->tk_z;
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
@@ -530,6 +544,7 @@ void create_plan(const ddstress_desc* desc, const ddstress_tuning* tuning, hipSt
         p->tk_y = lc.tk_y;
         p->ey = lc.ey;
         p->ez = lc.ez;
+        p->yx = lc.yx;
         const Shape& s = p->shape;
         p->spec = std::make_shared<DevBuf>();
         p->tw = std::make_shared<DevBuf>();
@@ -670,6 +685,25 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
             out->ms[2] = ms;
         }
     }
+    // inverse y and x: the chosen separate passes against the fused kernel
+    out->yx = 1;
+    if constexpr (sizeof(T) == 4) {
+        if (yx_ok(s)) {
+            ColGeom gi{};
+            gi.ncols = s.M1; gi.n_in = Py; gi.n_out = Ny; gi.nouter = 1; gi.nplanes = B6 * Nz;
+            gi.irs = s.wx; gi.ips = (int64_t)Py * s.wx; gi.ors = s.wx; gi.ops = (int64_t)Ny * s.wx;
+            const float sep = time_median(st, reps, [&] {
+                launch_col_fft<T>(Py, out->ey, false, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gi, twp, out->tk_y, st);
+                launch_x_c2r<T>(s.M, out->ex, w2.as<cplx<T>>(), sig.as<T>(), B6 * Nz * Ny, Nx, s.wx, Nx, twp,
+                                out->rows_x, st);
+            });
+            const float fused = time_median(st, reps, [&] {
+                launch_yx_inv(w1.as<cplx<float>>(), sig.as<float>(), B6 * Nz, Py, s.M, Ny, Nx, s.wx, twp, st);
+            });
+            if (verbose) std::fprintf(stderr, "[tune] inverse y+x separate %.5f ms fused %.5f ms\n", sep, fused);
+            if (fused < sep) out->yx = 2;
+        }
+    }
     check_hip(hipStreamSynchronize(st), "tuning");
 }
 
@@ -785,6 +819,7 @@ ddstress_status ddstress_plan_share(ddstress_plan src, int32_t batch, ddstress_p
             p->ex = src->ex;
             p->ey = src->ey;
             p->ez = src->ez;
+            p->yx = src->yx;
             p->re_max = src->re_max;
             p->im_max = src->im_max;
             const Shape& s = p->shape;
@@ -834,6 +869,7 @@ ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info) 
         info->ey = plan->ey;
         info->ez = plan->ez;
         info->z_groups = s.zg;
+        info->yx_fused = plan->yx ? 1 : 0;
         info->cached_bytes = plan->spec->bytes + plan->tw->bytes;
         info->work_bytes = plan->work1.bytes + plan->work2.bytes + plan->rho_own.bytes + plan->sigma_tmp.bytes;
         info->kernel_real_max = plan->re_max;

@@ -219,7 +219,7 @@ struct RowPad {        // element i of row r at r*ld + i + (i >> s): one pad ele
 // the length-R DFT and writes (b / Ns) Ns R + (b mod Ns) + r Ns.
 template <typename T, int N, int E, bool FWD, int Ns, int R, class Lay>
 __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
-                                          const cplx<T>* __restrict__ tw) {
+                                          const cplx<T>* __restrict__ tw, bool act) {
     constexpr int Tc = N / E;
     constexpr int NB = E / R;
     constexpr bool first = (Ns == 1);
@@ -232,10 +232,12 @@ __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay l
             for (int r = 0; r < R; ++r) v[q][r] = reg[q + r * NB];
     } else {
         __syncthreads();
+        if (act) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q)
+            for (int q = 0; q < NB; ++q)
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = lds[lay(j + Tc * q + r * (N / R), c)];
+                for (int r = 0; r < R; ++r) v[q][r] = lds[lay(j + Tc * q + r * (N / R), c)];
+        }
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -253,23 +255,25 @@ __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay l
             for (int r = 0; r < R; ++r) reg[q + r * NB] = v[q][r];
     } else {
         __syncthreads();   // every thread has read its inputs (or the buffer's previous user is done)
+        if (act) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int b = j + Tc * q;
-            const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
+            for (int q = 0; q < NB; ++q) {
+                const int b = j + Tc * q;
+                const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[lay(base + r * Ns, c)] = v[q][r];
+                for (int r = 0; r < R; ++r) lds[lay(base + r * Ns, c)] = v[q][r];
+            }
         }
     }
 }
 
 template <typename T, int N, int E, bool FWD, int Ns, class Lay>
 __device__ __forceinline__ void fft_stages(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
-                                           const cplx<T>* __restrict__ tw) {
+                                           const cplx<T>* __restrict__ tw, bool act) {
     if constexpr (Ns < N) {
         constexpr int R = cmin(cmin(8, E), N / Ns);
-        fft_stage<T, N, E, FWD, Ns, R>(reg, lds, lay, c, j, tw);
-        fft_stages<T, N, E, FWD, Ns * R>(reg, lds, lay, c, j, tw);
+        fft_stage<T, N, E, FWD, Ns, R>(reg, lds, lay, c, j, tw, act);
+        fft_stages<T, N, E, FWD, Ns * R>(reg, lds, lay, c, j, tw, act);
     }
 }
 
@@ -447,12 +451,13 @@ __device__ __forceinline__ void fft_regs_k(cplx<T> (&reg)[K][E], const cplx<T> (
 
 // Full transform of length N on the register distribution described above.
 // `tw` points at the table of exp(-2 pi i k / N), k < N. Every thread of the
-// block must call it (it contains barriers when N > E).
+// block must call it (it contains barriers when N > E); threads with act ==
+// false (whole waves) take part in the barriers without touching LDS.
 template <typename T, int N, int E, bool FWD, class Lay>
 __device__ __forceinline__ void fft_regs(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
-                                         const cplx<T>* __restrict__ tw) {
+                                         const cplx<T>* __restrict__ tw, bool act = true) {
     static_assert(N % E == 0, "E must divide N");
-    fft_stages<T, N, E, FWD, 1>(reg, lds, lay, c, j, tw);
+    fft_stages<T, N, E, FWD, 1>(reg, lds, lay, c, j, tw, act);
 }
 
 }  // namespace dds

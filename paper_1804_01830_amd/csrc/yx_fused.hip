@@ -1,0 +1,134 @@
+// Fused inverse y and inverse x (complex-to-real) of planes that fit in one
+// block's LDS. After the fused z pass, every (realisation, stress component,
+// z) plane holds Py rows of M+1 complex values (kx); the plain path transforms
+// its kx columns back along y into Ny rows (written to memory) and then each
+// row back along x into Nx reals (read again). Here one block of 1024 threads
+// keeps the Ny x (M+1) intermediate plane in LDS, so it never travels to
+// memory:
+//   1. the kx columns are transformed along y in rounds of 16-column groups;
+//      each group exchanges through its own LDS region placed after the plane
+//      columns already finished, so the number of groups per round is what
+//      the remaining LDS holds (64, 48, 16 and 1 columns at Py = 256, M = 128);
+//      rows y < Ny go to the plane, stored as column c at c (Py/2) + (y ^ (c & 15))
+//      (the XOR spreads a group's 16 columns over the banks);
+//   2. each row is combined into Z'[k] = (X[k] + conj X[M-k]) + i exp(+2 pi i k / P)
+//      (X[k] - conj X[M-k]) (the same split as k_x_c2r), transformed along x
+//      with the plane's LDS reused for the exchanges, and written as Nx reals.
+// The arithmetic is that of the two plain passes (same transforms, same
+// element classes), so results are identical.
+#include "ddstress_internal.hpp"
+
+namespace dds {
+
+namespace {
+
+constexpr int kYXThreads = 1024;
+constexpr int kYXLds = 160 * 1024;       // LDS per block on gfx950
+
+template <int PY, int M>
+__global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __restrict__ in, float* __restrict__ out,
+                                                       int ny, int nx, int64_t wx, const cplx<float>* __restrict__ tw,
+                                                       int xld, int xsh, int pairs) {
+    using T = float;
+    constexpr int M1 = M + 1;
+    constexpr int PLD = PY / 2;                          // plane column stride: rows y < Py/2
+    constexpr int GC = 16, EY = 16, TCY = PY / EY;       // y: 16 columns per group, Tc threads per column
+    constexpr int GT = GC * TCY;                         // threads per group
+    constexpr int CAP = kYXLds / (int)sizeof(cplx<T>);
+    constexpr int EX = 16, TCX = M / EX;                 // x: Tc threads per row
+    static_assert(kYXThreads % GT == 0 && kYXThreads / TCX >= PY / 2, "launch shape");
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int t = threadIdx.x;
+    const int64_t plane = blockIdx.x;
+    const cplx<T>* src = in + plane * (int64_t)PY * wx;
+
+    // 1. inverse y of the kx columns, rounds of groups
+    {
+        const int gi = t / GT, tl = t % GT, cl = tl % GC, j = tl / GC;
+        for (int c0 = 0; c0 < M1;) {
+            int groups = (CAP - c0 * PLD) / (PY * GC);
+            if (groups > kYXThreads / GT) groups = kYXThreads / GT;
+            const int ncols = groups * GC < M1 - c0 ? groups * GC : M1 - c0;
+            groups = (ncols + GC - 1) / GC;
+            const bool act = gi < groups;                // whole waves
+            const int c = c0 + gi * GC + cl;
+            const bool valid = act && c < M1;
+            cplx<T> reg[EY];
+#pragma unroll
+            for (int m = 0; m < EY; ++m)
+                reg[m] = valid ? src[(int64_t)(j + TCY * m) * wx + c] : cplx<T>{T(0), T(0)};
+            cplx<T>* scratch = lds + c0 * PLD + (act ? gi : 0) * (PY * GC);
+            fft_regs<T, PY, EY, false>(reg, scratch, ColMajor{GC}, cl, j, tw + (PY - 1), act);
+            __syncthreads();                             // the groups' last exchange reads are done
+            if (valid) {
+#pragma unroll
+                for (int m = 0; m < (EY + 1) / 2; ++m) {    // rows y = j + Tc m < Py/2
+                    const int y = j + TCY * m;
+                    if (y < ny) lds[c * PLD + (y ^ (c & 15))] = reg[m];
+                }
+            }
+            c0 += ncols;
+        }
+    }
+    __syncthreads();
+
+    // 2. per row: split into Z', inverse x, Nx reals
+    const int j = t % TCX, y = t / TCX;
+    const bool row_ok = y < ny;
+    const cplx<T>* tw2 = tw + (2 * M - 1);
+    cplx<T> reg[EX];
+#pragma unroll
+    for (int m = 0; m < EX; ++m) {
+        const int k = j + TCX * m;
+        const int km = M - k;
+        const int yr = row_ok ? y : 0;
+        const cplx<T> xk = lds[k * PLD + (yr ^ (k & 15))];
+        const cplx<T> xm = cconj(lds[km * PLD + (yr ^ (km & 15))]);
+        const cplx<T> e = cadd(xk, xm);
+        const cplx<T> wd = twmul<false>(csub(xk, xm), tw2[k]);   // exp(+2 pi i k/P) (X[k] - conj X[M-k])
+        reg[m] = {e.x - wd.y, e.y + wd.x};                       // e + i wd
+    }
+    __syncthreads();                                 // the plane is read: its LDS serves the x exchanges
+    fft_regs<T, M, EX, false>(reg, lds, RowPad{xld, xsh}, y, j, tw + (M - 1));
+    if (!row_ok) return;
+    T* dst = out + plane * (int64_t)ny * nx + (int64_t)y * nx;
+    if (pairs) {
+        cplx<T>* dst2 = reinterpret_cast<cplx<T>*>(dst);
+#pragma unroll
+        for (int m = 0; m < EX; ++m) {
+            const int q = j + TCX * m;
+            if (2 * q < nx) dst2[q] = reg[m];
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < EX; ++m) {
+            const int i0 = 2 * (j + TCX * m);
+            if (i0 < nx) dst[i0] = reg[m].x;
+            if (i0 + 1 < nx) dst[i0 + 1] = reg[m].y;
+        }
+    }
+}
+
+}  // namespace
+
+bool yx_inv_fits(int Py, int M, int ny, int elem_bytes) {
+    if (elem_bytes != 4 || Py != 256 || M != 128 || ny < 1 || ny > Py / 2) return false;
+    const XLayout xl = x_lds_layout(M, 16, elem_bytes);
+    return (size_t)(Py / 2) * xl.ld * 2 * elem_bytes <= (size_t)kYXLds &&
+           (size_t)(M + 1) * (Py / 2) * 2 * elem_bytes <= (size_t)kYXLds;
+}
+
+void launch_yx_inv(const cplx<float>* in, float* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
+                   const cplx<float>* tw, hipStream_t s) {
+    if (nplanes <= 0) return;
+    if (!yx_inv_fits(Py, M, ny, 4)) fail(DDSTRESS_E_INVALID, "plane does not fit the fused inverse y-x kernel");
+    if (nplanes > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
+    const XLayout xl = x_lds_layout(M, 16, 4);
+    const int pairs = (reinterpret_cast<uintptr_t>(out) % 8 == 0 && nx % 2 == 0) ? 1 : 0;
+    hipLaunchKernelGGL((k_yx_inv<256, 128>), dim3((unsigned)nplanes), dim3(kYXThreads), kYXLds, s, in, out, ny, nx,
+                       wx, tw, xl.ld, xl.s, pairs);
+    check_hip(hipGetLastError(), "fused inverse y-x launch");
+}
+
+}  // namespace dds

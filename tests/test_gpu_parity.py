@@ -40,6 +40,8 @@ CASES = {
     "rand-512x2x2-max-x": lambda: W.random_field((512, 2, 2), n_lines=1, seed=11),
     "rand-2x512x2-max-y": lambda: W.random_field((2, 512, 2), n_lines=1, seed=11),
     "rand-2x2x512-max-z-L3": lambda: W.random_field((2, 2, 512), n_lines=3, seed=11),
+    # planes that take the fused inverse y-x kernel in FP32 (Px = Py = 256)
+    "rand-72x70x2-B2": lambda: W.random_field((72, 70, 2), n_lines=1, batch=2, seed=13, d=(1.0, 1.0, 2.0)),
 }
 
 
