@@ -104,6 +104,7 @@ typedef struct {
     int32_t ex, ey, ez;    /* element classes of the x, y and fused z passes (see ddstress_tuning) */
     int32_t z_groups;      /* thread groups per column tile of the fused z pass (see ddstress_tuning) */
     int32_t yx_fused;      /* 1: inverse y and inverse x run as one kernel (see ddstress_tuning) */
+    int32_t xy_fused;      /* 1: forward x and forward y run as one kernel (see ddstress_tuning) */
     int32_t mirror_y;      /* 1: every coefficient plane is even or odd under y -> -y (each line direction
                               has t_y = 0 or is parallel to e_y), so the spectrum is kept for ky <= Py/2
                               only, with a sign per plane for the mirrored rows */
@@ -134,6 +135,7 @@ typedef struct {
     int32_t yx;            /* inverse y and x: 1 two passes, 2 one fused kernel that keeps each
                               (realisation, component, z) plane in LDS (FP32 with Py = 256 and
                               Px = 256 only), 0 default (fused where it applies) */
+    int32_t xy;            /* forward x and y: 1 two passes, 2 one fused kernel (same shapes), 0 default */
     float   ms[3];         /* autotune: median device ms of the chosen x pair, y pair and z pass */
 } ddstress_tuning;
 
@@ -156,7 +158,7 @@ ddstress_status ddstress_plan_footprint(const ddstress_desc* desc, size_t* cache
 ddstress_status ddstress_plan_create(const ddstress_desc* desc, void* stream, ddstress_plan* out);
 
 /* Autotuner: times every admissible tile size, element class and z group
- * count of each pass, and the fused against the separate inverse y and x (threads per block <= 512, 768 for the grouped z pass;
+ * count of each pass, and the fused against the separate x and y passes (threads per block <= 512, 768 for the grouped z pass;
  * LDS <= 64 KiB) on zero-filled buffers of the descriptor's
  * shape, precision and batch, with HIP events on `stream` (median of five runs
  * after two warm-up runs), and returns the fastest per pass. Synchronous;

@@ -34,7 +34,8 @@ class Desc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("rows_x", ctypes.c_int32), ("tk_y", ctypes.c_int32), ("tk_z", ctypes.c_int32),
                 ("ex", ctypes.c_int32), ("ey", ctypes.c_int32), ("ez", ctypes.c_int32),
-                ("z_groups", ctypes.c_int32), ("yx", ctypes.c_int32), ("ms", ctypes.c_float * 3)]
+                ("z_groups", ctypes.c_int32), ("yx", ctypes.c_int32), ("xy", ctypes.c_int32),
+                ("ms", ctypes.c_float * 3)]
 
 
 class Info(ctypes.Structure):
@@ -42,7 +43,7 @@ class Info(ctypes.Structure):
                 ("batch", ctypes.c_int32), ("precision", ctypes.c_int32), ("tile_z", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("rows_x", ctypes.c_int32), ("ex", ctypes.c_int32),
                 ("ey", ctypes.c_int32), ("ez", ctypes.c_int32), ("z_groups", ctypes.c_int32),
-                ("yx_fused", ctypes.c_int32), ("mirror_y", ctypes.c_int32),
+                ("yx_fused", ctypes.c_int32), ("xy_fused", ctypes.c_int32), ("mirror_y", ctypes.c_int32),
                 ("mirror_z", ctypes.c_int32),
                 ("cached_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t),
                 ("kernel_real_max", ctypes.c_double), ("kernel_imag_max", ctypes.c_double)]

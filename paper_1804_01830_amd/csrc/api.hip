@@ -196,6 +196,7 @@ struct ddstress_plan_s {
     int rows_x = 1, tk_y = 1;      // x rows and y columns per block
     int ex = 16, ey = 16, ez = 8;  // element classes of the x, y and fused z passes
     bool yx = false;               // inverse y and x as one kernel
+    bool xy = false;               // forward x and y as one kernel
     double re_max = 0.0, im_max = 0.0;
     // per-pass event timing: events are pooled and reused between folds
     bool profiling = false;
@@ -376,21 +377,32 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2], Py = s.P[1];
     p->mark(st);
     // x forward: rows (b, c, z, y) of Nx reals -> M+1 complex
-    launch_x_r2c<T>(s.M, p->ex, rho, w1, BC * Nz * Ny, Nx, Nx, s.wx, tw, p->rows_x, st);
-    p->mark(st);
-    // y forward: Ny rows -> Py rows
-    ColGeom gy{};
-    gy.ncols = s.M1;
-    gy.n_in = Ny;
-    gy.n_out = Py;
-    gy.nouter = 1;
-    gy.nplanes = BC * Nz;
-    gy.irs = s.wx;
-    gy.ips = (int64_t)Ny * s.wx;
-    gy.ors = s.wx;
-    gy.ops = (int64_t)Py * s.wx;
-    launch_col_fft<T>(Py, p->ey, true, w1, w2, gy, tw, p->tk_y, st);
-    p->mark(st);
+    bool fused_fwd = false;
+    if constexpr (sizeof(T) == 4) {
+        if (p->xy) {        // one kernel; the y pass's time shows as zero
+            launch_xy_fwd(rho, w2, BC * Nz, Py, s.M, Ny, Nx, s.wx, tw, st);
+            p->mark(st);
+            p->mark(st);
+            fused_fwd = true;
+        }
+    }
+    if (!fused_fwd) {
+        launch_x_r2c<T>(s.M, p->ex, rho, w1, BC * Nz * Ny, Nx, Nx, s.wx, tw, p->rows_x, st);
+        p->mark(st);
+        // y forward: Ny rows -> Py rows
+        ColGeom gy{};
+        gy.ncols = s.M1;
+        gy.n_in = Ny;
+        gy.n_out = Py;
+        gy.nouter = 1;
+        gy.nplanes = BC * Nz;
+        gy.irs = s.wx;
+        gy.ips = (int64_t)Ny * s.wx;
+        gy.ors = s.wx;
+        gy.ops = (int64_t)Py * s.wx;
+        launch_col_fft<T>(Py, p->ey, true, w1, w2, gy, tw, p->tk_y, st);
+        p->mark(st);
+    }
     // z forward + contraction + z inverse
     ZGeom gz{};
     gz.nky_s = s.nkys;
@@ -502,14 +514,14 @@ bool z_ok(const Shape& s, int tk, int ev, int groups) {
 
 struct LaunchChoice {
     int rows_x, ex, tk_y, ey, ez, zg;
-    bool yx;
+    bool yx, xy;
 };
 
 bool yx_ok(const Shape& s) { return yx_inv_fits(s.P[1], s.M, s.N[1], s.elem); }
 
 LaunchChoice default_launch(const Shape& s) {
     return {default_rows(s.M, s.elem), default_ev_col(s.M), default_col_tk(s.P[1], s.elem), default_ev_col(s.P[1]),
-            default_ev_z(s.P[2], s.zg, s.elem), s.zg, yx_ok(s)};
+            default_ev_z(s.P[2], s.zg, s.elem), s.zg, yx_ok(s), yx_ok(s)};
 }
 
 // Apply a tuning (zero element classes select the defaults) after checking it.
@@ -521,9 +533,9 @@ LaunchChoice apply_tuning(Shape& s, const ddstress_tuning* t) {
     const int ez = t->ez ? t->ez : default_ev_z(s.P[2], zg, s.elem);
     if (!rows_ok(s, t->rows_x, ex) || !col_ok(s, s.P[1], t->tk_y, ey) || !z_ok(s, t->tk_z, ez, zg))
         fail(DDSTRESS_E_INVALID, "tuning choice outside the launch limits of this shape");
-    if (t->yx < 0 || t->yx > 2 || (t->yx == 2 && !yx_ok(s)))
-        fail(DDSTRESS_E_INVALID, "fused inverse y-x does not apply to this shape");
-    c = {t->rows_x, ex, t->tk_y, ey, ez, zg, t->yx == 0 ? yx_ok(s) : t->yx == 2};
+    if (t->yx < 0 || t->yx > 2 || (t->yx == 2 && !yx_ok(s)) || t->xy < 0 || t->xy > 2 || (t->xy == 2 && !yx_ok(s)))
+        fail(DDSTRESS_E_INVALID, "fused x-y passes do not apply to this shape");
+    c = {t->rows_x, ex, t->tk_y, ey, ez, zg, t->yx == 0 ? yx_ok(s) : t->yx == 2, t->xy == 0 ? yx_ok(s) : t->xy == 2};
     s.zg = zg;
     s.tkz = t->tk_z;
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
@@ -545,6 +557,7 @@ void create_plan(const ddstress_desc* desc, const ddstress_tuning* tuning, hipSt
         p->ey = lc.ey;
         p->ez = lc.ez;
         p->yx = lc.yx;
+        p->xy = lc.xy;
         const Shape& s = p->shape;
         p->spec = std::make_shared<DevBuf>();
         p->tw = std::make_shared<DevBuf>();
@@ -685,8 +698,9 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
             out->ms[2] = ms;
         }
     }
-    // inverse y and x: the chosen separate passes against the fused kernel
+    // inverse y and x, forward x and y: the chosen separate passes against the fused kernels
     out->yx = 1;
+    out->xy = 1;
     if constexpr (sizeof(T) == 4) {
         if (yx_ok(s)) {
             ColGeom gi{};
@@ -702,6 +716,19 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
             });
             if (verbose) std::fprintf(stderr, "[tune] inverse y+x separate %.5f ms fused %.5f ms\n", sep, fused);
             if (fused < sep) out->yx = 2;
+            ColGeom gy{};
+            gy.ncols = s.M1; gy.n_in = Ny; gy.n_out = Py; gy.nouter = 1; gy.nplanes = BC * Nz;
+            gy.irs = s.wx; gy.ips = (int64_t)Ny * s.wx; gy.ors = s.wx; gy.ops = (int64_t)Py * s.wx;
+            const float sepf = time_median(st, reps, [&] {
+                launch_x_r2c<T>(s.M, out->ex, rho.as<T>(), w1.as<cplx<T>>(), BC * Nz * Ny, Nx, Nx, s.wx, twp,
+                                out->rows_x, st);
+                launch_col_fft<T>(Py, out->ey, true, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gy, twp, out->tk_y, st);
+            });
+            const float fusedf = time_median(st, reps, [&] {
+                launch_xy_fwd(rho.as<float>(), w2.as<cplx<float>>(), BC * Nz, Py, s.M, Ny, Nx, s.wx, twp, st);
+            });
+            if (verbose) std::fprintf(stderr, "[tune] forward x+y separate %.5f ms fused %.5f ms\n", sepf, fusedf);
+            out->xy = fusedf < sepf ? 2 : 1;
         }
     }
     check_hip(hipStreamSynchronize(st), "tuning");
@@ -820,6 +847,7 @@ ddstress_status ddstress_plan_share(ddstress_plan src, int32_t batch, ddstress_p
             p->ey = src->ey;
             p->ez = src->ez;
             p->yx = src->yx;
+            p->xy = src->xy;
             p->re_max = src->re_max;
             p->im_max = src->im_max;
             const Shape& s = p->shape;
@@ -870,6 +898,7 @@ ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info) 
         info->ez = plan->ez;
         info->z_groups = s.zg;
         info->yx_fused = plan->yx ? 1 : 0;
+        info->xy_fused = plan->xy ? 1 : 0;
         info->cached_bytes = plan->spec->bytes + plan->tw->bytes;
         info->work_bytes = plan->work1.bytes + plan->work2.bytes + plan->rho_own.bytes + plan->sigma_tmp.bytes;
         info->kernel_real_max = plan->re_max;

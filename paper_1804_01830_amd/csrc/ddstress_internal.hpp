@@ -106,10 +106,12 @@ template <typename T, int NC, bool GROUPED>
 void z_dispatch(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
                 const cplx<T>* tw, int tk, int64_t blocks, hipStream_t s);
 
-// Fused inverse y and inverse x for planes that fit one block's LDS
-// (yx_fused.hip): FP32, Py = 256, M = 128.
+// Fused forward x and y, and fused inverse y and x, for planes that fit one
+// block's LDS (yx_fused.hip): FP32, Py = 256, M = 128.
 bool yx_inv_fits(int Py, int M, int ny, int elem_bytes);
 void launch_yx_inv(const cplx<float>* in, float* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
+                   const cplx<float>* tw, hipStream_t s);
+void launch_xy_fwd(const float* in, cplx<float>* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
                    const cplx<float>* tw, hipStream_t s);
 
 // Every power-of-two transform length the passes support.

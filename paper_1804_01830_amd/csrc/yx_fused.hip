@@ -1,5 +1,8 @@
-// Fused inverse y and inverse x (complex-to-real) of planes that fit in one
-// block's LDS. After the fused z pass, every (realisation, stress component,
+// Fused x and y passes of planes that fit in one block's LDS: the inverse
+// y and inverse x (complex-to-real) after the z pass, and the forward x
+// (real-to-complex) and forward y before it.
+//
+// Inverse. After the fused z pass, every (realisation, stress component,
 // z) plane holds Py rows of M+1 complex values (kx); the plain path transforms
 // its kx columns back along y into Ny rows (written to memory) and then each
 // row back along x into Nx reals (read again). Here one block of 1024 threads
@@ -14,8 +17,17 @@
 //   2. each row is combined into Z'[k] = (X[k] + conj X[M-k]) + i exp(+2 pi i k / P)
 //      (X[k] - conj X[M-k]) (the same split as k_x_c2r), transformed along x
 //      with the plane's LDS reused for the exchanges, and written as Nx reals.
-// The arithmetic is that of the two plain passes (same transforms, same
-// element classes), so results are identical.
+// The arithmetic is that of the two plain passes at element class 16 (same
+// transforms), so results are identical.
+//
+// Forward. Every (realisation, channel, z) plane of the density holds Ny rows
+// of Nx reals. One block transforms each row along x (real-to-complex, the
+// split of k_x_r2c) and keeps the (M+1) x Ny spectrum plane in LDS, column c
+// at (M - c) (Py/2) + (y ^ (c & 15)) (reversed, so the columns consumed first
+// free a contiguous range at the end), then transforms the kx columns along y
+// (rows >= Ny are the zero padding) in rounds of 16-column groups whose
+// exchange regions take the LDS freed so far (16, 32, 64 and 17 columns at
+// Py = 256, M = 128), writing the Py rows of each column.
 #include "ddstress_internal.hpp"
 
 namespace dds {
@@ -110,6 +122,112 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
     }
 }
 
+
+template <int PY, int M>
+__global__ void __launch_bounds__(kYXThreads) k_xy_fwd(const float* __restrict__ in, cplx<float>* __restrict__ out,
+                                                       int ny, int nx, int64_t wx, const cplx<float>* __restrict__ tw,
+                                                       int xld, int xsh, int pairs) {
+    using T = float;
+    constexpr int M1 = M + 1;
+    constexpr int PLD = PY / 2;
+    constexpr int GC = 16, EY = 16, TCY = PY / EY;
+    constexpr int GT = GC * TCY;
+    constexpr int CAP = kYXLds / (int)sizeof(cplx<T>);
+    constexpr int EX = 16, TCX = M / EX;
+    static_assert(kYXThreads % GT == 0 && kYXThreads / TCX >= PY / 2, "launch shape");
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    const int t = threadIdx.x;
+    const int64_t plane = blockIdx.x;
+
+    // 1. per row: reals in pairs, length-M transform, split into M+1 outputs
+    {
+        const int j = t % TCX, y = t / TCX;
+        const bool row_ok = y < ny;
+        const T* src = in + plane * (int64_t)ny * nx + (int64_t)(row_ok ? y : 0) * nx;
+        cplx<T> reg[EX];
+        if (pairs) {
+            const cplx<T>* src2 = reinterpret_cast<const cplx<T>*>(src);
+#pragma unroll
+            for (int m = 0; m < EX; ++m) {
+                const int q = j + TCX * m;
+                reg[m] = (row_ok && 2 * q < nx) ? src2[q] : cplx<T>{T(0), T(0)};
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < EX; ++m) {
+                const int i0 = 2 * (j + TCX * m);
+                T a = T(0), b = T(0);
+                if (row_ok && i0 < nx) a = src[i0];
+                if (row_ok && i0 + 1 < nx) b = src[i0 + 1];
+                reg[m] = {a, b};
+            }
+        }
+        const RowPad lay{xld, xsh};
+        fft_regs<T, M, EX, true>(reg, lds, lay, y, j, tw + (M - 1));
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < EX; ++m) lds[lay(j + TCX * m, y)] = reg[m];
+        __syncthreads();
+        const cplx<T>* tw2 = tw + (2 * M - 1);
+        const T half = T(0.5);
+        cplx<T> xs[EX];
+#pragma unroll
+        for (int m = 0; m < EX; ++m) {
+            const int k = j + TCX * m;
+            const cplx<T> zk = lds[lay(k, y)];
+            const cplx<T> zm = cconj(lds[lay((M - k) & (M - 1), y)]);
+            const cplx<T> e = cadd(zk, zm);
+            const cplx<T> wd = cmul(tw2[k], csub(zk, zm));          // W_P^k (Z[k] - conj Z[M-k])
+            xs[m] = {half * (e.x + wd.y), half * (e.y - wd.x)};     // e/2 - (i/2) wd
+        }
+        const cplx<T> z0 = lds[lay(0, y)];
+        __syncthreads();                                 // the row spectra are read: the plane takes their LDS
+        if (row_ok) {
+#pragma unroll
+            for (int m = 0; m < EX; ++m) {
+                const int k = j + TCX * m;
+                lds[(M - k) * PLD + (y ^ (k & 15))] = xs[m];
+            }
+            if (j == 0) lds[0 * PLD + (y ^ (M & 15))] = cplx<T>{z0.x - z0.y, T(0)};     // column M
+        }
+    }
+    __syncthreads();
+
+    // 2. forward y of the kx columns, rounds of groups growing into the freed LDS
+    {
+        cplx<T>* dst = out + plane * (int64_t)PY * wx;
+        const int gi = t / GT, tl = t % GT, cl = tl % GC, j = tl / GC;
+        for (int c0 = 0; c0 < M1;) {
+            int groups = kYXThreads / GT, ncols = 0;
+            for (; groups > 1; --groups) {
+                ncols = groups * GC < M1 - c0 ? groups * GC : M1 - c0;
+                const int g2 = (ncols + GC - 1) / GC;
+                if (g2 * PY * GC <= CAP - (M1 - c0 - ncols) * PLD) break;
+            }
+            ncols = groups * GC < M1 - c0 ? groups * GC : M1 - c0;
+            groups = (ncols + GC - 1) / GC;
+            const bool act = gi < groups;
+            const int c = c0 + gi * GC + cl;
+            const bool valid = act && c < M1;
+            cplx<T> reg[EY];
+#pragma unroll
+            for (int m = 0; m < EY; ++m) {
+                const int y = j + TCY * m;
+                reg[m] = (valid && 2 * m < EY && y < ny) ? lds[(M - c) * PLD + (y ^ (c & 15))]
+                                                         : cplx<T>{T(0), T(0)};
+            }
+            cplx<T>* scratch = lds + (M1 - c0 - ncols) * PLD + (act ? gi : 0) * (PY * GC);
+            fft_regs<T, PY, EY, true>(reg, scratch, ColMajor{GC}, cl, j, tw + (PY - 1), act);
+            if (valid) {
+#pragma unroll
+                for (int m = 0; m < EY; ++m) dst[(int64_t)(j + TCY * m) * wx + c] = reg[m];
+            }
+            c0 += ncols;
+        }
+    }
+}
+
 }  // namespace
 
 bool yx_inv_fits(int Py, int M, int ny, int elem_bytes) {
@@ -117,6 +235,18 @@ bool yx_inv_fits(int Py, int M, int ny, int elem_bytes) {
     const XLayout xl = x_lds_layout(M, 16, elem_bytes);
     return (size_t)(Py / 2) * xl.ld * 2 * elem_bytes <= (size_t)kYXLds &&
            (size_t)(M + 1) * (Py / 2) * 2 * elem_bytes <= (size_t)kYXLds;
+}
+
+void launch_xy_fwd(const float* in, cplx<float>* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
+                   const cplx<float>* tw, hipStream_t s) {
+    if (nplanes <= 0) return;
+    if (!yx_inv_fits(Py, M, ny, 4)) fail(DDSTRESS_E_INVALID, "plane does not fit the fused forward x-y kernel");
+    if (nplanes > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
+    const XLayout xl = x_lds_layout(M, 16, 4);
+    const int pairs = (reinterpret_cast<uintptr_t>(in) % 8 == 0 && nx % 2 == 0) ? 1 : 0;
+    hipLaunchKernelGGL((k_xy_fwd<256, 128>), dim3((unsigned)nplanes), dim3(kYXThreads), kYXLds, s, in, out, ny, nx,
+                       wx, tw, xl.ld, xl.s, pairs);
+    check_hip(hipGetLastError(), "fused forward x-y launch");
 }
 
 void launch_yx_inv(const cplx<float>* in, float* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,

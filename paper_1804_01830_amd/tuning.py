@@ -18,7 +18,7 @@ def cache_path():
 
 
 # Part of every key: entries written for other launch-shape fields are not reused.
-LAYOUT = "z3"
+LAYOUT = "z4"
 
 
 def device_tag():
@@ -53,7 +53,7 @@ def _write(path, data):
 
 def to_dict(t):
     return {"rows_x": t.rows_x, "tk_y": t.tk_y, "tk_z": t.tk_z, "ex": t.ex, "ey": t.ey, "ez": t.ez,
-            "z_groups": t.z_groups, "yx": t.yx, "ms": [round(float(v), 5) for v in t.ms]}
+            "z_groups": t.z_groups, "yx": t.yx, "xy": t.xy, "ms": [round(float(v), 5) for v in t.ms]}
 
 
 def from_dict(d):
@@ -62,6 +62,7 @@ def from_dict(d):
     t.ex, t.ey, t.ez = int(d.get("ex", 0)), int(d.get("ey", 0)), int(d.get("ez", 0))
     t.z_groups = int(d.get("z_groups", 0))
     t.yx = int(d.get("yx", 0))
+    t.xy = int(d.get("xy", 0))
     for i, v in enumerate(d.get("ms", [0, 0, 0])[:3]):
         t.ms[i] = float(v)
     return t

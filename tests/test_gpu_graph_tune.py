@@ -150,21 +150,21 @@ def test_tuning_outside_limits_is_rejected():
 
 @pytest.mark.parametrize("grid", [(128, 128, 4), (100, 77, 3), (65, 128, 2)])
 def test_fused_inverse_yx_gives_separate_bits(grid):
-    """The fused inverse y-x kernel (planes kept in LDS) gives the bits of the
-    separate inverse y and inverse x passes at the same element class (16),
-    on full and ragged planes, with several realisations."""
+    """The fused inverse y-x and forward x-y kernels (planes kept in LDS) give
+    the bits of the separate passes at the same element class (16), on full
+    and ragged planes, with several realisations."""
     import torch
     from paper_1804_01830_amd import binding as B
     w = W.random_field(grid, n_lines=1, batch=2, seed=21, d=(1.0, 1.0, 2.0))
     desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=32, batch=2)
     base = B.Plan(desc).info()
     outs = []
-    for yx in (1, 2):
+    for yx, xy in ((1, 1), (2, 1), (1, 2), (2, 2)):
         t = B.Tuning()
         t.rows_x, t.tk_y, t.tk_z = base.rows_x, base.tile_y, base.tile_z
-        t.ex, t.ey, t.ez, t.z_groups, t.yx = 16, 16, base.ez, base.z_groups, yx
+        t.ex, t.ey, t.ez, t.z_groups, t.yx, t.xy = 16, 16, base.ez, base.z_groups, yx, xy
         plan = B.Plan(desc, tuning=t)
-        assert plan.info().yx_fused == (yx == 2)
+        assert plan.info().yx_fused == (yx == 2) and plan.info().xy_fused == (xy == 2)
         rho = torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32)
         out = plan.new_output()
         plan.set_density(rho)
@@ -172,7 +172,8 @@ def test_fused_inverse_yx_gives_separate_bits(grid):
         torch.cuda.synchronize()
         outs.append(out)
         plan.close()
-    assert torch.equal(outs[0], outs[1])
+    for o in outs[1:]:
+        assert torch.equal(outs[0], o)
 
 
 def test_fused_inverse_yx_refused_where_it_does_not_fit():
@@ -184,4 +185,8 @@ def test_fused_inverse_yx_refused_where_it_does_not_fit():
     with pytest.raises(B.DDStressError) as e:
         B.Plan(desc, tuning=t)
     assert e.value.status == B.E_INVALID
-    assert d.yx_fused == 0
+    t.yx, t.xy = 0, 2
+    with pytest.raises(B.DDStressError) as e:
+        B.Plan(desc, tuning=t)
+    assert e.value.status == B.E_INVALID
+    assert d.yx_fused == 0 and d.xy_fused == 0
