@@ -63,17 +63,23 @@ def z_pass_bytes(info, n, C, B, elem):
 
 
 def path_bytes(info, n, C, B, elem):
-    """Algorithmic HBM bytes of the whole five-pass path for one call."""
+    """Algorithmic HBM bytes of the whole path for one call: five passes, or
+    fewer where the plan fuses the x and y passes (the intermediate plane then
+    stays in LDS and is not counted)."""
     Px, Py, Pz = info.padded
     Nx, Ny, Nz = n
     M1 = Px // 2 + 1
     cx = 2 * M1                       # reals per complex x-spectrum row
-    xf = elem * B * C * Nz * Ny * (Nx + cx)
-    yf = elem * B * C * Nz * M1 * 2 * (Ny + Py)
+    if info.xy_fused:                 # density reals in, y spectra out
+        fwd = elem * B * C * Nz * (Ny * Nx + M1 * 2 * Py)
+    else:
+        fwd = elem * B * C * Nz * Ny * (Nx + cx) + elem * B * C * Nz * M1 * 2 * (Ny + Py)
     z = z_pass_bytes(info, n, C, B, elem)
-    yi = elem * B * 6 * Nz * M1 * 2 * (Py + Ny)
-    xi = elem * B * 6 * Nz * Ny * (cx + Nx)
-    return xf + yf + z + yi + xi
+    if info.yx_fused:                 # z output in, stress reals out
+        inv = elem * B * 6 * Nz * (M1 * 2 * Py + Ny * Nx)
+    else:
+        inv = elem * B * 6 * Nz * M1 * 2 * (Py + Ny) + elem * B * 6 * Nz * Ny * (cx + Nx)
+    return fwd + z + inv
 
 
 def time_path(plan, rho, out, steps, warmup, profile, graph=False):
@@ -352,6 +358,7 @@ def main():
                 "algorithmic_bytes_per_launch": int(zbytes), "avg_launch_ms": round(z_ms, 5)}
     plan_info = {"padded": list(info32.padded), "tile_z": info32.tile_z, "ez": info32.ez,
                  "z_groups": info32.z_groups, "mirror_y": info32.mirror_y, "mirror_z": info32.mirror_z,
+                 "xy_fused": info32.xy_fused, "yx_fused": info32.yx_fused,
                  "rows_x": info32.rows_x, "tile_y": info32.tile_y, "ex": info32.ex, "ey": info32.ey}
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "cells/s", "n_gpus": 1,
