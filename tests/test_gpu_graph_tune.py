@@ -151,8 +151,8 @@ def test_tuning_outside_limits_is_rejected():
 @pytest.mark.parametrize("grid", [(128, 128, 4), (100, 77, 3), (65, 128, 2)])
 def test_fused_inverse_yx_gives_separate_bits(grid):
     """The fused inverse y-x and forward x-y kernels (planes kept in LDS) give
-    the bits of the separate passes at the same element class (16), on full
-    and ragged planes, with several realisations."""
+    the bits of the separate passes at the same element classes (x 16, y 8),
+    on full and ragged planes, with several realisations."""
     import torch
     from paper_1804_01830_amd import binding as B
     w = W.random_field(grid, n_lines=1, batch=2, seed=21, d=(1.0, 1.0, 2.0))
@@ -162,7 +162,7 @@ def test_fused_inverse_yx_gives_separate_bits(grid):
     for yx, xy in ((1, 1), (2, 1), (1, 2), (2, 2)):
         t = B.Tuning()
         t.rows_x, t.tk_y, t.tk_z = base.rows_x, base.tile_y, base.tile_z
-        t.ex, t.ey, t.ez, t.z_groups, t.yx, t.xy = 16, 16, base.ez, base.z_groups, yx, xy
+        t.ex, t.ey, t.ez, t.z_groups, t.yx, t.xy = 16, 8, base.ez, base.z_groups, yx, xy
         plan = B.Plan(desc, tuning=t)
         assert plan.info().yx_fused == (yx == 2) and plan.info().xy_fused == (xy == 2)
         rho = torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32)
