@@ -82,6 +82,14 @@ def path_bytes(info, n, C, B, elem):
     return fwd + z + inv
 
 
+def b_pass_bytes(C, B, elem):
+    """Bytes per cell of the plain five-pass model, s (13 C + 24 C / B + 78):
+    forward passes, the kernel spectrum read once per batch, inverse passes.
+    value x b_pass_bytes / 8 TB/s is the fraction of the HBM roofline that
+    model allows (fused planes move fewer bytes than it counts)."""
+    return elem * (13 * C + 24 * C / B + 78)
+
+
 def time_path(plan, rho, out, steps, warmup, profile, graph=False):
     import torch
     from paper_1804_01830_amd import binding as Bd
@@ -381,6 +389,7 @@ def main():
         "pass_ms": {k: round(v / max(r32["calls"], 1), 5) for k, v in r32["passes"].items()},
         "path_algorithmic_gbs": round(pbytes / (ms32 * 1e-3) / 1e9, 1),
         "path_frac": round(pbytes / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "b_pass_frac": round(value * b_pass_bytes(C, B, elem) / (HBM_PEAK_GBS * 1e9), 4),
         "host_to_host": {"value": round(cells / (r32["host"]["wall"] / r32["host"]["steps"]), 1),
                          "ms_per_step": round(r32["host"]["wall"] / r32["host"]["steps"] * 1e3, 5),
                          "p50_ms": round(pct(r32["host"]["per"], 50) * 1e3, 5),

@@ -190,3 +190,33 @@ def test_fused_inverse_yx_refused_where_it_does_not_fit():
         B.Plan(desc, tuning=t)
     assert e.value.status == B.E_INVALID
     assert d.yx_fused == 0 and d.xy_fused == 0
+
+
+def test_fused_planes_with_graphs_and_partial_batches():
+    """A plan whose x-y passes are fused (planes in LDS, 1024-thread blocks
+    walking over planes): graph replays, with eager work between them, and
+    calls on the first realisations only give the bits of direct full calls."""
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w = W.random_field((100, 70, 2), n_lines=1, batch=3, seed=23, d=(1.0, 1.0, 2.0))
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=32, batch=3)
+    plan = B.Plan(desc)
+    info = plan.info()
+    assert info.yx_fused == 1 and info.xy_fused == 1
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32).contiguous()
+    ref = torch.empty((3, 6, 2, 70, 100), dtype=torch.float32, device="cuda")
+    plan.stress_batch(rho, ref, 3)
+    two = torch.empty((2, 6, 2, 70, 100), dtype=torch.float32, device="cuda")
+    plan.stress_batch(rho[:2], two, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(two, ref[:2])
+    plan.set_graph(True)
+    out = torch.empty_like(ref)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        plan.stress_batch(rho, out, 3)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {rep}"
+        junk = torch.randn(1 << 18, device="cuda").sum()
+        assert torch.isfinite(junk)
+    plan.close()
