@@ -192,22 +192,10 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
-// Elements per thread used for a transform of length N in the plain passes.
-constexpr int elems_for(int N) { return N <= 8 ? N : (N <= 64 ? 8 : 16); }
-// Elements per thread in the fused z kernel (six complex accumulators per
-// element must stay in registers: 8 in FP32, 4 in FP64).
-constexpr int elems_fused(int N, int elem_bytes) {
-    return elem_bytes <= 4 ? (N <= 8 ? N : 8) : (N <= 4 ? N : 4);
-}
-
 // LDS addressing of element i of transform (column / row) c.
 struct ColMajor {      // element i of column c at i*ld + c (tiles of consecutive columns)
     int ld;
     __device__ __forceinline__ int operator()(int i, int c) const { return i * ld + c; }
-};
-struct RowMajor {      // element i of row r at r*ld + i
-    int ld;
-    __device__ __forceinline__ int operator()(int i, int r) const { return r * ld + i; }
 };
 struct RowPad {        // element i of row r at r*ld + i + (i >> s): one pad element every 2^s
     int ld, s;
@@ -278,9 +266,9 @@ __device__ __forceinline__ void fft_stages(cplx<T> (&reg)[E], cplx<T>* lds, Lay 
 }
 
 // Twiddles of every stage after the first, for the butterflies one thread
-// owns: count, load (once) and a stage that takes them from registers. A
-// kernel that runs many transforms of one length keeps them for all of them
-// (the inverse uses their conjugates).
+// owns: their count and a load (once); fftk_stage takes them from registers.
+// A kernel that runs many transforms of one length keeps them for all of
+// them (the inverse uses their conjugates).
 constexpr int tw_count(int N, int E, int Ns = 1) {
     return Ns >= N ? 0
                    : (Ns == 1 ? 0 : (E / cmin(cmin(8, E), N / Ns)) * (cmin(cmin(8, E), N / Ns) - 1)) +
@@ -305,69 +293,6 @@ __device__ __forceinline__ void load_tw_stages(cplx<T> (&w)[TWC], int j, const c
             load_tw_stages<T, N, E, Ns * R, K>(w, j, tw);
         }
     }
-}
-
-template <typename T, int N, int E, bool FWD, int Ns, int R, int K, int TWC, class Lay>
-__device__ __forceinline__ void fft_stage_tw(cplx<T> (&reg)[E], const cplx<T> (&w)[TWC], cplx<T>* lds, Lay lay,
-                                             int c, int j) {
-    constexpr int Tc = N / E;
-    constexpr int NB = E / R;
-    constexpr bool first = (Ns == 1);
-    constexpr bool last = (Ns * R == N);
-    cplx<T> v[NB][R];
-    if constexpr (first) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = reg[q + r * NB];
-    } else {
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[q][r] = lds[lay(j + Tc * q + r * (N / R), c)];
-    }
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        if constexpr (!first) {
-#pragma unroll
-            for (int r = 1; r < R; ++r) v[q][r] = twmul<FWD>(v[q][r], w[K + q * (R - 1) + r - 1]);
-        }
-        dftR<R, FWD>(v[q]);
-    }
-    if constexpr (last) {
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-#pragma unroll
-            for (int r = 0; r < R; ++r) reg[q + r * NB] = v[q][r];
-    } else {
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            const int b = j + Tc * q;
-            const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
-#pragma unroll
-            for (int r = 0; r < R; ++r) lds[lay(base + r * Ns, c)] = v[q][r];
-        }
-    }
-}
-
-template <typename T, int N, int E, bool FWD, int Ns, int K, int TWC, class Lay>
-__device__ __forceinline__ void fft_stages_tw(cplx<T> (&reg)[E], const cplx<T> (&w)[TWC], cplx<T>* lds, Lay lay,
-                                              int c, int j) {
-    if constexpr (Ns < N) {
-        constexpr int R = cmin(cmin(8, E), N / Ns);
-        fft_stage_tw<T, N, E, FWD, Ns, R, K, TWC>(reg, w, lds, lay, c, j);
-        fft_stages_tw<T, N, E, FWD, Ns * R, (Ns == 1 ? K : K + (E / R) * (R - 1)), TWC>(reg, w, lds, lay, c, j);
-    }
-}
-
-// Transform with the twiddles already in registers (see load_tw_stages).
-template <typename T, int N, int E, bool FWD, int TWC, class Lay>
-__device__ __forceinline__ void fft_regs_tw(cplx<T> (&reg)[E], const cplx<T> (&w)[TWC], cplx<T>* lds, Lay lay, int c,
-                                            int j) {
-    static_assert(N % E == 0, "E must divide N");
-    fft_stages_tw<T, N, E, FWD, 1, 0, TWC>(reg, w, lds, lay, c, j);
 }
 
 // K transforms of length N taken through the stages together, with the
