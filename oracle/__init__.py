@@ -24,6 +24,9 @@ What the oracle computes, in the paper's order:
   theorem with ``scipy.fft`` (a library primitive). Used only as a
   full-field reference on grids where the direct sum is too slow; it is
   pinned to ``direct`` on small grids.
+* ``periodic``: periodic boundary conditions in the layer plane (Sec. 4):
+  the replica-shell interaction function Eq. (13), the periodic direct sum
+  Eq. (12) and its library-FFT reference (circular convolution at the period).
 
 Every function is FP64. Readings of points where the paper is silent or
 ambiguous are stated in the docstring that applies them.
@@ -33,9 +36,11 @@ from .segment import (VOIGT, segment_stress, segment_stress_vertical,
 from .kernel import KernelGeometry, interaction_kernel, kernel_table
 from .direct import stress_direct
 from .fft_reference import stress_fft_reference
+from .periodic import periodic_kernel, stress_direct_periodic, stress_fft_reference_periodic
 
 __all__ = [
     "VOIGT", "segment_stress", "segment_stress_vertical", "segment_stress_general",
     "chord_length", "KernelGeometry", "interaction_kernel", "kernel_table",
     "stress_direct", "stress_fft_reference",
+    "periodic_kernel", "stress_direct_periodic", "stress_fft_reference_periodic",
 ]
