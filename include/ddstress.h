@@ -15,8 +15,11 @@
  * The computed quantity, for every cell r0 of the grid,
  *     sigma_v(r0) = sum_{cells i} sum_{c < C} K_{v,c}(r0 - r_i) rho_c(r_i),
  * is Eq. (10) summed over the dislocation types of Eq. (3b). Cell (i, j, k)
- * has its centre at (i dx, j dy, k dz). The sample sits in an infinite
- * medium: open boundaries, no periodic images.
+ * has its centre at (i dx, j dy, k dz). By default the sample sits in an
+ * infinite medium: open boundaries, no periodic images. With
+ * DDSTRESS_FLAG_PERIODIC_X and/or _Y the sample is continued periodically in
+ * the layer plane (Sec. 4): K is replaced by its sum over replica shells,
+ * Eq. (12)-(13), and the sum over cells runs over one period.
  *
  * Density channels. A plan has L line directions t_l (1 <= L <= 3) and
  * C = 3L density channels; channel c = 3 l + gamma holds the line density
@@ -84,8 +87,27 @@ typedef struct {
     int32_t batch;         /* B >= 1 densities per stress() call sharing this plan */
     int32_t near_shells;   /* S: a cell offset D is subdivided when |D_a| d_a <= S max(d) on every
                               axis; 0 selects the default 2, negative is invalid */
-    uint32_t flags;        /* 0 or DDSTRESS_FLAG_FULL_SPECTRUM */
+    uint32_t flags;        /* OR of DDSTRESS_FLAG_*; other bits are DDSTRESS_E_UNSUPPORTED */
+    int32_t pbc_shells;    /* n_sh: replica shells |k|, |l| <= n_sh of Eq. (13) along the periodic axes;
+                              0 selects the default 15, 1..32 as given, negative is invalid, above 32
+                              unsupported; ignored without a periodic flag */
 } ddstress_desc;
+
+/* Periodic boundary conditions along x (y) in the layer plane (Sec. 4). The
+ * axis is transformed at its own length, so N_a must be a power of two
+ * (2..512; DDSTRESS_E_UNSUPPORTED otherwise), and the coefficient of a cell
+ * offset D is
+ *     F(D) = sum_{|k|, |l| <= n_sh} K(D' + (k Nx, l Ny, 0))
+ * (Eq. 13, k only along a periodic x, l only along a periodic y), where D' is
+ * D reduced into [-N_a/2, N_a/2) on each periodic axis, and at the half period
+ * D'_a = -N_a/2 the mean of the sums around -N_a/2 and +N_a/2 is taken (the
+ * two representatives are equally central; the mean keeps F odd, as K is).
+ * A replica term is subdivided when its own offset is near; only the central
+ * term of D = 0 is the zero self-term. z is never periodic. Costs
+ * (2 n_sh + 1)^2 times the coefficient evaluations of an open plan at build
+ * time and nothing per call. */
+#define DDSTRESS_FLAG_PERIODIC_X 1u
+#define DDSTRESS_FLAG_PERIODIC_Y 2u
 
 /* Store the kernel spectrum for every wavevector even where a mirror symmetry
  * would let half of it be reconstructed (see ddstress_info.mirror_y). */
@@ -93,7 +115,8 @@ typedef struct {
 
 /* Read-only facts about a plan. */
 typedef struct {
-    int32_t padded[3];     /* FFT lengths Px, Py, Pz: powers of two >= max(2, 2 N_a - 1) */
+    int32_t padded[3];     /* FFT lengths Px, Py, Pz: powers of two >= max(2, 2 N_a - 1); N_a on a
+                              periodic axis */
     int32_t subdiv[3];     /* subcells per axis m_a = max(1, floor(d_a / min(d) + 1/2)) */
     int32_t channels;      /* C = 3 L */
     int32_t batch;         /* B */
@@ -234,8 +257,9 @@ ddstress_status ddstress_plan_destroy(ddstress_plan plan);
  * written in FP64 to the device buffer `out` laid out [3][6][Pz][Py][Px]
  * (Burgers component gamma, Voigt component, then the padded grid in wrap
  * order: index i on axis a holds offset i for i < N_a, i - P_a for
- * i > P_a - N_a, and zero in between). `out` must hold 18 Px Py Pz doubles.
- * Enqueued on `stream`. */
+ * i > P_a - N_a, and zero in between; on a periodic axis P_a = N_a and index i
+ * holds the replica sum F of offset i modulo N_a). `out` must hold
+ * 18 Px Py Pz doubles. Enqueued on `stream`. */
 ddstress_status ddstress_kernel_realspace(const ddstress_desc* desc, int32_t line, double* out,
                                           void* stream);
 

@@ -63,18 +63,32 @@ def periodic_kernel(geom, offsets, n, periodic, shells):
     return out
 
 
-def stress_direct_periodic(rho, d, lines, mu, nu, periodic=(True, True), shells=15, near_shells=2):
+def stress_direct_periodic(rho, d, lines, mu, nu, periodic=(True, True), shells=15, near_shells=2,
+                           targets=None):
     """Stress by direct summation over one period of source cells with the
     replica-summed interaction function.
 
     rho: (C, Nz, Ny, Nx) FP64 channels (C = 3 * len(lines)); returns
-    (6, Nz, Ny, Nx), Voigt order (xx, yy, zz, yz, xz, xy)."""
+    (6, Nz, Ny, Nx), Voigt order (xx, yy, zz, yz, xz, xy). With ``targets``
+    (T, 3) integer cells (i, j, k) it returns (6, T) and sums over the source
+    cells that carry density only (a cell whose channels are all zero adds
+    nothing), so a sparse density on a large grid stays cheap."""
     rho = np.asarray(rho, dtype=np.float64)
     C, nz, ny, nx = rho.shape
     lines = np.asarray(lines, dtype=np.float64).reshape(-1, 3)
     if C != 3 * len(lines):
         raise ValueError("rho must have 3 channels per line direction")
     geoms = _geoms(d, lines, mu, nu, near_shells)
+    if targets is not None:
+        targets = np.asarray(targets, dtype=np.int64).reshape(-1, 3)
+        kk, jj, ii = np.nonzero(np.any(rho != 0.0, axis=0))
+        src = np.stack([ii, jj, kk], axis=-1)
+        offs = (targets[:, None, :] - src[None, :, :]).reshape(-1, 3)       # (T * S, 3)
+        out = np.zeros((6, len(targets)))
+        for l, g in enumerate(geoms):
+            F = periodic_kernel(g, offs, (nx, ny, nz), periodic, shells).reshape(len(targets), len(src), 6, 3)
+            out += np.einsum("tsvg,gs->vt", F, rho[3 * l:3 * l + 3, kk, jj, ii])
+        return out
     # F on every offset Delta_a in (-N_a, N_a): (2nz-1, 2ny-1, 2nx-1, 6, 3)
     gz, gy, gx = np.meshgrid(np.arange(-(nz - 1), nz), np.arange(-(ny - 1), ny),
                              np.arange(-(nx - 1), nx), indexing="ij")

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libddstress.so")
 
 OK, E_INVALID, E_NOMEM, E_DEVICE, E_STATE, E_UNSUPPORTED = range(6)
-FLAG_FULL_SPECTRUM = 4
+FLAG_PERIODIC_X, FLAG_PERIODIC_Y, FLAG_FULL_SPECTRUM = 1, 2, 4
 HOST, DEVICE_COPY, DEVICE_BORROW = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STATE", 5: "E_UNSUPPORTED"}
 
@@ -28,7 +28,7 @@ class Desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("d", ctypes.c_double * 3), ("mu", ctypes.c_double),
                 ("nu", ctypes.c_double), ("n_lines", ctypes.c_int32), ("t", (ctypes.c_double * 3) * 3),
                 ("precision", ctypes.c_int32), ("batch", ctypes.c_int32), ("near_shells", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("pbc_shells", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -101,7 +101,10 @@ def check(status):
         raise DDStressError(status, load().ddstress_last_error().decode())
 
 
-def make_desc(n, d, mu, nu, lines, precision=32, batch=1, near_shells=0, flags=0):
+def make_desc(n, d, mu, nu, lines, precision=32, batch=1, near_shells=0, flags=0, periodic=(False, False),
+              pbc_shells=0):
+    """Descriptor of a plan. ``periodic`` = (x, y) sets the periodic-boundary
+    flags; ``pbc_shells`` is the replica shell count (0: the default 15)."""
     desc = Desc()
     for a in range(3):
         desc.n[a] = int(n[a])
@@ -116,7 +119,8 @@ def make_desc(n, d, mu, nu, lines, precision=32, batch=1, near_shells=0, flags=0
     desc.precision = int(precision)
     desc.batch = int(batch)
     desc.near_shells = int(near_shells)
-    desc.flags = int(flags)
+    desc.flags = int(flags) | (FLAG_PERIODIC_X if periodic[0] else 0) | (FLAG_PERIODIC_Y if periodic[1] else 0)
+    desc.pbc_shells = int(pbc_shells)
     return desc
 
 
@@ -253,9 +257,14 @@ def kernel_realspace(desc, line, out, stream=None):
     return out
 
 
-def padded_lengths(n):
+def padded_lengths(n, periodic=(False, False)):
+    """FFT lengths of a plan: N on a periodic axis, else the power of two
+    >= max(2, 2N - 1)."""
     out = []
-    for v in n:
+    for a, v in enumerate(n):
+        if a < 2 and periodic[a]:
+            out.append(int(v))
+            continue
         p = 1
         while p < 2 * v - 1:
             p *= 2

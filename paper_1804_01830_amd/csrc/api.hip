@@ -110,7 +110,15 @@ void validate(const ddstress_desc* d) {
     if (d->precision != 32 && d->precision != 64) fail(DDSTRESS_E_INVALID, "precision must be 32 or 64");
     if (d->batch < 1) fail(DDSTRESS_E_INVALID, "batch must be >= 1");
     if (d->near_shells < 0) fail(DDSTRESS_E_INVALID, "near_shells must be >= 0");
-    if ((d->flags & ~DDSTRESS_FLAG_FULL_SPECTRUM) != 0) fail(DDSTRESS_E_UNSUPPORTED, "unknown flag bits");
+    const uint32_t known = DDSTRESS_FLAG_PERIODIC_X | DDSTRESS_FLAG_PERIODIC_Y | DDSTRESS_FLAG_FULL_SPECTRUM;
+    if ((d->flags & ~known) != 0) fail(DDSTRESS_E_UNSUPPORTED, "unknown flag bits");
+    for (int a = 0; a < 2; ++a)
+        if (periodic_axis(d, a) && (d->n[a] < 2 || (d->n[a] & (d->n[a] - 1)) != 0))
+            fail(DDSTRESS_E_UNSUPPORTED, "a periodic axis needs a power-of-two size >= 2");
+    if (d->flags & (DDSTRESS_FLAG_PERIODIC_X | DDSTRESS_FLAG_PERIODIC_Y)) {
+        if (d->pbc_shells < 0) fail(DDSTRESS_E_INVALID, "pbc_shells must be >= 0");
+        if (d->pbc_shells > kMaxPbcShells) fail(DDSTRESS_E_UNSUPPORTED, "pbc_shells above 32 are not supported");
+    }
 }
 
 // A mirror a -> -a maps every line segment onto itself (possibly reversed)
@@ -139,7 +147,7 @@ Shape make_shape(const ddstress_desc* d) {
     Shape s{};
     for (int a = 0; a < 3; ++a) {
         s.N[a] = d->n[a];
-        s.P[a] = std::max(2, next_pow2(2 * d->n[a] - 1));
+        s.P[a] = (a < 2 && periodic_axis(d, a)) ? d->n[a] : std::max(2, next_pow2(2 * d->n[a] - 1));
     }
     s.M = s.P[0] / 2;
     s.M1 = s.M + 1;

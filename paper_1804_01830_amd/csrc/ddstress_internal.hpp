@@ -40,6 +40,13 @@ constexpr int kTwiddleEntries = 2 * kMaxLen;
 template <typename T>
 void fill_twiddles(cplx<T>* host);   // kTwiddleEntries entries
 
+// Periodic boundary conditions in the layer plane (axis 0: x, 1: y).
+inline bool periodic_axis(const ddstress_desc* d, int axis) {
+    return (d->flags & (axis == 0 ? DDSTRESS_FLAG_PERIODIC_X : DDSTRESS_FLAG_PERIODIC_Y)) != 0;
+}
+constexpr int kMaxPbcShells = 32;
+constexpr int kDefaultPbcShells = 15;
+
 // ---- pass launchers (passes.hip) -------------------------------------------
 // Real-to-complex transform of length P = 2M along contiguous rows.
 template <typename T>
@@ -130,6 +137,8 @@ struct KernelParams {
     double h_cell, h_sub;
     double dV;
     double near_lim;   // S * max(d)
+    int per[2];        // 1: x (y) periodic, P = N there, offsets summed over replica shells
+    int shells;        // replica shells n_sh of the periodic axes
 };
 KernelParams make_kernel_params(const ddstress_desc& desc, int line, const int P[3]);
 // 18 planes [gamma][v][Pz][Py][Px] of FP64 coefficients.

@@ -1,4 +1,5 @@
-// Interaction coefficients on the device, in FP64 (Sec. 2.2 and 2.3).
+// Interaction coefficients on the device, in FP64 (Sec. 2.2 and 2.3), and
+// their replica-shell sums for periodic boundaries in the plane (Sec. 4).
 //
 // For one line direction t and each unit Burgers vector e_gamma,
 //   K_{v,gamma}(D) = dV / h * sigma^AB_v(p; e_gamma, t, h)
@@ -92,8 +93,55 @@ __device__ __forceinline__ bool wrap_offset(int i, int n, int P, int& off) {
     return false;
 }
 
-// One thread per (x, y) point of one z plane of the padded grid: blockIdx.y
+// acc += w * K(D): one open-boundary coefficient (far: centre offset; near:
+// weighted sum over sub-offsets; D = 0: the zero self-term).
+__device__ void add_coefficient(const KernelParams& kp, const int D[3], double w, double* acc) {
+    if (D[0] == 0 && D[1] == 0 && D[2] == 0) return;
+    bool near = true;
+    for (int a = 0; a < 3; ++a) near = near && (fabs((double)D[a]) * kp.d[a] <= kp.near_lim);
+    if (!near) {
+        const double p[3] = {D[0] * kp.d[0], D[1] * kp.d[1], D[2] * kp.d[2]};
+        segment(p, kp.h_cell, kp.t, w * kp.dV / kp.h_cell, kp.mu, kp.nu, acc);
+        return;
+    }
+    for (int dz = -(kp.m[2] - 1); dz < kp.m[2]; ++dz)
+        for (int dy = -(kp.m[1] - 1); dy < kp.m[1]; ++dy)
+            for (int dx = -(kp.m[0] - 1); dx < kp.m[0]; ++dx) {
+                const double wx = (double)(kp.m[0] - abs(dx)) / (double)(kp.m[0] * kp.m[0]);
+                const double wy = (double)(kp.m[1] - abs(dy)) / (double)(kp.m[1] * kp.m[1]);
+                const double wz = (double)(kp.m[2] - abs(dz)) / (double)(kp.m[2] * kp.m[2]);
+                const double ws = wx * wy * wz;
+                const double p[3] = {D[0] * kp.d[0] + dx * kp.s[0], D[1] * kp.d[1] + dy * kp.s[1],
+                                     D[2] * kp.d[2] + dz * kp.s[2]};
+                segment(p, kp.h_sub, kp.t, w * ws * kp.dV / kp.h_sub, kp.mu, kp.nu, acc);
+            }
+}
+
+// Offsets represented by grid index i on one axis: the wrap-order offset of a
+// zero-padded axis (none in the padding gap), or on a periodic axis (P = N)
+// the representative in [-N/2, N/2), with both -N/2 and +N/2 at half weight
+// for the half period. Returns the number of representatives (0, 1 or 2).
+__device__ __forceinline__ int axis_reps(int i, int n, int P, bool periodic, int rep[2], double wt[2]) {
+    if (periodic) {
+        const int h = n / 2;
+        if (i == h && (n & 1) == 0) {
+            rep[0] = -h;
+            rep[1] = h;
+            wt[0] = wt[1] = 0.5;
+            return 2;
+        }
+        rep[0] = i <= h ? i : i - n;
+        wt[0] = 1.0;
+        return 1;
+    }
+    wt[0] = 1.0;
+    return wrap_offset(i, n, P, rep[0]) ? 1 : 0;
+}
+
+// One thread per (x, y) point of one z plane of the FFT grid: blockIdx.y
 // and blockIdx.z carry the y and z indices, so no 64-bit division is needed.
+// On a periodic axis the coefficient is the sum over the replica shells
+// |k|, |l| <= n_sh of the offset's representative (Eq. 13).
 __global__ void __launch_bounds__(256) k_kernel_build(double* __restrict__ out, KernelParams kp, int64_t plane) {
     const int ix = blockIdx.x * blockDim.x + threadIdx.x;
     const int iy = blockIdx.y;
@@ -102,28 +150,23 @@ __global__ void __launch_bounds__(256) k_kernel_build(double* __restrict__ out, 
     const int64_t idx = ((int64_t)iz * kp.P[1] + iy) * kp.P[0] + ix;
     double acc[18];
     for (int q = 0; q < 18; ++q) acc[q] = 0.0;
-    int D[3];
-    const bool inside = wrap_offset(ix, kp.n[0], kp.P[0], D[0]) && wrap_offset(iy, kp.n[1], kp.P[1], D[1]) &&
-                        wrap_offset(iz, kp.n[2], kp.P[2], D[2]);
-    if (inside && (D[0] != 0 || D[1] != 0 || D[2] != 0)) {
-        bool near = true;
-        for (int a = 0; a < 3; ++a) near = near && (fabs((double)D[a]) * kp.d[a] <= kp.near_lim);
-        if (!near) {
-            const double p[3] = {D[0] * kp.d[0], D[1] * kp.d[1], D[2] * kp.d[2]};
-            segment(p, kp.h_cell, kp.t, kp.dV / kp.h_cell, kp.mu, kp.nu, acc);
-        } else {
-            for (int dz = -(kp.m[2] - 1); dz < kp.m[2]; ++dz)
-                for (int dy = -(kp.m[1] - 1); dy < kp.m[1]; ++dy)
-                    for (int dx = -(kp.m[0] - 1); dx < kp.m[0]; ++dx) {
-                        const double wx = (double)(kp.m[0] - abs(dx)) / (double)(kp.m[0] * kp.m[0]);
-                        const double wy = (double)(kp.m[1] - abs(dy)) / (double)(kp.m[1] * kp.m[1]);
-                        const double wz = (double)(kp.m[2] - abs(dz)) / (double)(kp.m[2] * kp.m[2]);
-                        const double w = wx * wy * wz;
-                        const double p[3] = {D[0] * kp.d[0] + dx * kp.s[0], D[1] * kp.d[1] + dy * kp.s[1],
-                                             D[2] * kp.d[2] + dz * kp.s[2]};
-                        segment(p, kp.h_sub, kp.t, w * kp.dV / kp.h_sub, kp.mu, kp.nu, acc);
+    int rx[2], ry[2], dzv;
+    double wx[2], wy[2];
+    const int nx = axis_reps(ix, kp.n[0], kp.P[0], kp.per[0] != 0, rx, wx);
+    const int ny = axis_reps(iy, kp.n[1], kp.P[1], kp.per[1] != 0, ry, wy);
+    const bool zin = wrap_offset(iz, kp.n[2], kp.P[2], dzv);
+    const int sx = kp.per[0] ? kp.shells : 0;
+    const int sy = kp.per[1] ? kp.shells : 0;
+    if (zin) {
+        for (int a = 0; a < nx; ++a)
+            for (int b = 0; b < ny; ++b) {
+                const double w = wx[a] * wy[b];
+                for (int k = -sx; k <= sx; ++k)
+                    for (int l = -sy; l <= sy; ++l) {
+                        const int D[3] = {rx[a] + k * kp.n[0], ry[b] + l * kp.n[1], dzv};
+                        add_coefficient(kp, D, w, acc);
                     }
-        }
+            }
     }
     for (int q = 0; q < 18; ++q) out[q * plane + idx] = acc[q];
 }
@@ -255,6 +298,9 @@ KernelParams make_kernel_params(const ddstress_desc& desc, int line, const int P
     kp.dV = desc.d[0] * desc.d[1] * desc.d[2];
     const int S = desc.near_shells == 0 ? 2 : desc.near_shells;
     kp.near_lim = S * dmax;
+    kp.per[0] = periodic_axis(&desc, 0) ? 1 : 0;
+    kp.per[1] = periodic_axis(&desc, 1) ? 1 : 0;
+    kp.shells = desc.pbc_shells == 0 ? kDefaultPbcShells : desc.pbc_shells;
     return kp;
 }
 

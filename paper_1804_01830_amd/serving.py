@@ -34,6 +34,8 @@ class ShapeKey:
     lines: tuple          # tuple of 3-tuples
     precision: int = 32
     near_shells: int = 0
+    periodic: tuple = (False, False)     # periodic boundaries along x, y
+    pbc_shells: int = 0
 
     @property
     def cells(self):
@@ -237,7 +239,7 @@ class GpuExecutor:
 
     def _desc(self, key, batch):
         return self.B.make_desc(key.n, key.d, key.mu, key.nu, key.lines, precision=key.precision, batch=batch,
-                                near_shells=key.near_shells)
+                                near_shells=key.near_shells, periodic=key.periodic, pbc_shells=key.pbc_shells)
 
     def footprint(self, key, batch):
         cached, work, _ = self.B.footprint(self._desc(key, batch))

@@ -65,9 +65,11 @@ def disk_mixed(nx=128, ny=128, nz=32, d=(1.0, 1.0, 2.0), width=30.0, r_max=56.0,
                 lines=np.array([E_Z]), rho=rho)
 
 
-def voronoi_grains(nx, ny, n_grains, rng):
+def voronoi_grains(nx, ny, n_grains, rng, periodic=False):
     """Grain index per (y, x) cell: nearest of ``n_grains`` centres uniform in
-    [0, Nx) x [0, Ny), plain Euclidean distance, ties to the lowest index."""
+    [0, Nx) x [0, Ny), Euclidean distance (the minimum-image distance when
+    ``periodic``, so grains continue across the period), ties to the lowest
+    index."""
     cx = rng.uniform(0.0, nx, size=n_grains)
     cy = rng.uniform(0.0, ny, size=n_grains)
     x = np.arange(nx) + 0.5
@@ -75,7 +77,12 @@ def voronoi_grains(nx, ny, n_grains, rng):
     grain = np.zeros((ny, nx), dtype=np.int64)
     best = np.full((ny, nx), np.inf)
     for g in range(n_grains):
-        dist = (x[None, :] - cx[g]) ** 2 + (y[:, None] - cy[g]) ** 2
+        ddx = np.abs(x - cx[g])
+        ddy = np.abs(y - cy[g])
+        if periodic:
+            ddx = np.minimum(ddx, nx - ddx)
+            ddy = np.minimum(ddy, ny - ddy)
+        dist = ddx[None, :] ** 2 + ddy[:, None] ** 2
         closer = dist < best
         grain[closer] = g
         best[closer] = dist[closer]
@@ -83,8 +90,10 @@ def voronoi_grains(nx, ny, n_grains, rng):
 
 
 def poly_layer(nx=256, ny=256, nz=64, d=(1.0, 1.0, 2.0), grain=16.0, z_decay=8.0,
-               mu=1.0, nu=0.2, seed=3, p_mixed=0.5, batch_seeds=None):
-    """Columnar polycrystal layer; ``batch_seeds`` stacks several realisations."""
+               mu=1.0, nu=0.2, seed=3, p_mixed=0.5, batch_seeds=None, periodic=False):
+    """Columnar polycrystal layer; ``batch_seeds`` stacks several realisations.
+    ``periodic``: grains continue across the in-plane period (for plans with
+    periodic boundaries along x and y)."""
     seeds = [seed] if batch_seeds is None else list(batch_seeds)
     n_grains = max(1, int(round(nx * ny / float(grain) ** 2)))
     z = np.arange(nz) * d[2]
@@ -92,7 +101,7 @@ def poly_layer(nx=256, ny=256, nz=64, d=(1.0, 1.0, 2.0), grain=16.0, z_decay=8.0
     rho = np.zeros((len(seeds), 6, nz, ny, nx))
     for bi, sd in enumerate(seeds):
         rng = np.random.default_rng(sd)
-        gmap = voronoi_grains(nx, ny, n_grains, rng)
+        gmap = voronoi_grains(nx, ny, n_grains, rng, periodic)
         angle = np.radians(60.0) * rng.integers(0, 6, size=n_grains)
         is_mixed = rng.uniform(size=n_grains) < p_mixed
         bx = np.cos(angle)[gmap]
@@ -102,7 +111,7 @@ def poly_layer(nx=256, ny=256, nz=64, d=(1.0, 1.0, 2.0), grain=16.0, z_decay=8.0
             sel = (line == l).astype(np.float64)
             rho[bi, 3 * l + 0] = prof[:, None, None] * (sel * bx)[None]
             rho[bi, 3 * l + 1] = prof[:, None, None] * (sel * by)[None]
-    name = f"poly-layer-{nx}x{ny}x{nz}-g{grain:g}"
+    name = f"poly-layer{'-pbc' if periodic else ''}-{nx}x{ny}x{nz}-g{grain:g}"
     return dict(name=name, n=(nx, ny, nz), d=tuple(d), mu=mu, nu=nu,
                 lines=np.array([E_Z, mixed_line()]), rho=rho)
 

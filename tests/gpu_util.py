@@ -3,13 +3,13 @@ workload dict and compare with oracle results."""
 import numpy as np
 
 
-def gpu_stress(w, precision=64, near_shells=0, where_rho=None):
+def gpu_stress(w, precision=64, near_shells=0, where_rho=None, periodic=(False, False), pbc_shells=0):
     """sigma (B, 6, Nz, Ny, Nx) as float64 numpy, computed by the HIP library."""
     import torch
     from paper_1804_01830_amd import binding as B
     rho = np.asarray(w["rho"])
     desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision,
-                       batch=rho.shape[0], near_shells=near_shells)
+                       batch=rho.shape[0], near_shells=near_shells, periodic=periodic, pbc_shells=pbc_shells)
     plan = B.Plan(desc)
     dt = torch.float32 if precision == 32 else torch.float64
     r = torch.from_numpy(rho).to(device="cuda", dtype=dt).contiguous()

@@ -42,7 +42,7 @@ def test_footprint_of_a_valid_descriptor():
 @pytest.mark.parametrize("kw", [
     dict(n=(0, 8, 4)), dict(d=(1, -1, 2)), dict(d=(1, float("nan"), 2)), dict(mu=0.0), dict(nu=0.5),
     dict(nu=-1.0), dict(lines=[]), dict(lines=[(0, 0, 0)]), dict(lines=[(0, 0, 1)] * 4), dict(precision=16),
-    dict(batch=0), dict(near_shells=-1),
+    dict(batch=0), dict(near_shells=-1), dict(periodic=(True, False), pbc_shells=-1),
 ])
 def test_invalid_descriptors_are_rejected(kw):
     with pytest.raises(B.DDStressError) as e:
@@ -52,15 +52,30 @@ def test_invalid_descriptors_are_rejected(kw):
 
 
 def test_unsupported_sizes_and_flags():
-    for kw in (dict(n=(513, 8, 8)), dict(flags=1)):
+    for kw in (dict(n=(513, 8, 8)), dict(flags=8), dict(n=(6, 8, 4), periodic=(True, False)),
+               dict(n=(8, 12, 4), periodic=(False, True)), dict(n=(1, 8, 4), periodic=(True, True)),
+               dict(periodic=(True, True), pbc_shells=33)):
         with pytest.raises(B.DDStressError) as e:
             B.footprint(_desc(**kw))
         assert e.value.status == B.E_UNSUPPORTED
 
 
+def test_periodic_descriptors():
+    # a non-power-of-two x is fine while only y is periodic; the shell count is
+    # ignored without a periodic flag
+    for kw in (dict(n=(6, 8, 4), periodic=(False, True)), dict(pbc_shells=-1),
+               dict(periodic=(True, True), pbc_shells=32), dict(n=(2, 2, 1), periodic=(True, True))):
+        B.footprint(_desc(**kw))
+    open_ = B.footprint(_desc(n=(16, 16, 4)))
+    per = B.footprint(_desc(n=(16, 16, 4), periodic=(True, True)))
+    assert per[1] < open_[1] and per[2] < open_[2]
+
+
 def test_padded_lengths():
     assert B.padded_lengths((32, 128, 1)) == (64, 256, 2)
     assert B.padded_lengths((5, 3, 7)) == (16, 8, 16)
+    assert B.padded_lengths((32, 128, 8), periodic=(True, False)) == (32, 256, 16)
+    assert B.padded_lengths((32, 128, 8), periodic=(True, True)) == (32, 128, 16)
 
 
 def test_footprint_predicts_mirror_compression():

@@ -173,3 +173,25 @@ def test_replica_shells_converge_within_three_percent():
         nrm = np.linalg.norm(F20[m])
         assert np.linalg.norm(F15[m] - F20[m]) < 0.03 * nrm
         assert np.linalg.norm(F15[m] - F20[m]) < np.linalg.norm(F10[m] - F20[m])
+
+
+def test_sampled_targets_match_the_full_periodic_sum():
+    lines = np.array([(0, 0, 1), TILT])
+    rho = _rho(13, (4, 4, 3), 2)
+    rho[:, :, 1, :] = 0.0                         # some empty source cells
+    d = (1.0, 1.5, 2.0)
+    full = stress_direct_periodic(rho, d, lines, 1.0, 0.3, periodic=(True, False), shells=2)
+    tg = np.array([[0, 0, 0], [3, 1, 2], [2, 3, 1], [1, 2, 0]])
+    samp = stress_direct_periodic(rho, d, lines, 1.0, 0.3, periodic=(True, False), shells=2, targets=tg)
+    assert np.abs(samp - full[:, tg[:, 2], tg[:, 1], tg[:, 0]]).max() < 1e-13 * np.abs(full).max()
+
+
+def test_single_layer_of_the_smallest_period_has_zero_stress():
+    # every offset of a 2 x 2 x 1 period is 0 or a half period in the plane and
+    # 0 along z: F is odd and periodic there, so it vanishes
+    lines = np.array([(0, 0, 1), TILT])
+    rho = _rho(17, (2, 2, 1), 2)
+    out = stress_direct_periodic(rho, (1.0, 1.5, 2.0), lines, 1.0, 0.3, shells=4)
+    ref = stress_direct_periodic(rho, (1.0, 1.5, 2.0), lines, 1.0, 0.3, periodic=(False, False))
+    assert np.abs(ref).max() > 1e-2
+    assert np.abs(out).max() < 1e-14 * np.abs(ref).max() * 100
