@@ -31,8 +31,12 @@ def device_tag():
 
 
 def shape_key(desc, device_name=""):
+    """Cache key: the transform lengths follow from the grid and the periodic
+    axes, the launch shapes from those, the precision, channels and batch."""
     n = "x".join(str(v) for v in desc.n)
-    return f"{device_name}|{n}|fp{desc.precision}|C{3 * desc.n_lines}|B{desc.batch}|{LAYOUT}"
+    per = "".join(a for a, bit in (("x", 1), ("y", 2)) if desc.flags & bit)
+    pbc = f"|pbc{per}" if per else ""
+    return f"{device_name}|{n}{pbc}|fp{desc.precision}|C{3 * desc.n_lines}|B{desc.batch}|{LAYOUT}"
 
 
 def _read(path):

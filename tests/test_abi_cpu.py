@@ -89,3 +89,11 @@ def test_footprint_predicts_mirror_compression():
     spec_full = full - 2048 * 8            # minus the FP32 twiddle table
     spec_both = both - 2048 * 8
     assert spec_both * 16 * 8 == spec_full * 9 * 5
+
+
+def test_tuning_key_separates_periodic_plans():
+    from paper_1804_01830_amd import tuning as Tn
+    a = Tn.shape_key(_desc(n=(16, 16, 4)), "gfx950-256cu")
+    b = Tn.shape_key(_desc(n=(16, 16, 4), periodic=(True, True)), "gfx950-256cu")
+    c = Tn.shape_key(_desc(n=(16, 16, 4), periodic=(False, True)), "gfx950-256cu")
+    assert len({a, b, c}) == 3 and "pbc" not in a and "pbcxy" in b and "pbcy" in c
