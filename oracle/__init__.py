@@ -27,6 +27,9 @@ What the oracle computes, in the paper's order:
 * ``periodic``: periodic boundary conditions in the layer plane (Sec. 4):
   the replica-shell interaction function Eq. (13), the periodic direct sum
   Eq. (12) and its library-FFT reference (circular convolution at the period).
+* ``relax``: relaxation of the stress under free top and bottom surfaces
+  (Sec. 5): force density Eq. (15), traction conditions Eq. (16c) on ghost
+  layers Eq. (18b), explicit pseudo-time steps of Eq. (17), total stress.
 
 Every function is FP64. Readings of points where the paper is silent or
 ambiguous are stated in the docstring that applies them.
