@@ -263,6 +263,76 @@ ddstress_status ddstress_plan_destroy(ddstress_plan plan);
 ddstress_status ddstress_kernel_realspace(const ddstress_desc* desc, int32_t line, double* out,
                                           void* stream);
 
+/* ---- Relaxation under free surfaces (Sec. 5, Eq. 14-18) --------------------
+ *
+ * A film of Nx x Ny x Nz nodes (cell centres), periodic in x and y (Eq. 16a),
+ * with traction-free top and bottom surfaces through the first and the last
+ * node layer (Eq. 16b). Given the dislocation stress sigma^dis on the nodes
+ * (for example the output of ddstress_stress), the displacement u solves the
+ * Navier-Cauchy equation Eq. (14),
+ *     A grad div u - B rot rot u + f = 0,   f = div sigma^dis (Eq. 15),
+ * A = lambda + 2 mu, B = mu, with the surface conditions Eq. (16c), and the
+ * total stress is sigma^dis + sigma(u) (Hooke's law). u is found as the
+ * stationary state of the explicit pseudo-time iteration Eq. (17):
+ *     u <- u + dt (A grad div u - B rot rot u + f)
+ * with central differences (second differences for the Laplacian, products
+ * of central first differences for the mixed derivatives; f by central
+ * differences, second-order one-sided on the two surface layers) and ghost
+ * layers below and above the film rewritten after every step from Eq. (16c)
+ * (Eq. 18b and its analogues). The caller chooses the number of steps (the
+ * paper gives no stopping rule) and may watch ddstress_relax_update_norm.
+ *
+ * Layouts (float when precision == 32, double when 64), x fastest:
+ *   sigma^dis, sigma_total: [6][Nz][Ny][Nx], Voigt order (xx, yy, zz, yz, xz, xy)
+ *   u (with ghost layers):  [3][Nz + 2][Ny][Nx]; layer k + 1 holds node layer k
+ * All pointers are device memory. */
+typedef struct ddstress_relax_s* ddstress_relax;
+
+typedef struct {
+    int32_t n[3];          /* Nx, Ny >= 1, Nz >= 3 node layers; at most 4096 per axis */
+    double  d[3];          /* node spacings dx, dy, dz > 0 */
+    double  mu;            /* shear modulus > 0 (B of Eq. 14) */
+    double  nu;            /* Poisson ratio, -1 < nu < 0.5 */
+    int32_t precision;     /* 32 or 64 */
+    double  dt;            /* pseudo-time step; 0 selects min(d)^2 / (5A - 3B) (Sec. 5), negative is
+                              invalid. That step is stable for cubic cells when nu > 1/8 */
+} ddstress_relax_desc;
+
+typedef struct {
+    double  dt;            /* the step in use */
+    double  A, B;          /* moduli of Eq. (14) */
+    size_t  work_bytes;    /* device bytes held (two displacement states, force, surface terms) */
+    int64_t steps;         /* steps taken since the last ddstress_relax_set_load */
+} ddstress_relax_info;
+
+/* Allocate a relaxation plan. Synchronous; no load yet. */
+ddstress_status ddstress_relax_create(const ddstress_relax_desc* desc, ddstress_relax* out);
+
+/* Take the load: computes f (Eq. 15) and the surface terms of Eq. (16c)
+ * from sigma_dis and resets u to zero (ghost layers from Eq. 16c). sigma_dis
+ * is read during the call's kernels only. Enqueued on `stream`. */
+ddstress_status ddstress_relax_set_load(ddstress_relax r, const void* sigma_dis, void* stream);
+
+/* Enqueue n_steps >= 0 explicit steps of Eq. (17) on `stream`.
+ * DDSTRESS_E_STATE before set_load. */
+ddstress_status ddstress_relax_iterate(ddstress_relax r, int32_t n_steps, void* stream);
+
+/* max over the nodes of |A grad div u - B rot rot u + f| for the current u:
+ * the size of the next step's update divided by dt. Synchronises `stream`. */
+ddstress_status ddstress_relax_update_norm(ddstress_relax r, double* out, void* stream);
+
+/* sigma_total = sigma_dis + sigma(u) on the nodes (sigma_total may be
+ * sigma_dis itself). Enqueued on `stream`. */
+ddstress_status ddstress_relax_stress(ddstress_relax r, const void* sigma_dis, void* sigma_total, void* stream);
+
+/* Copy the current u with its ghost layers into `u`. Enqueued on `stream`. */
+ddstress_status ddstress_relax_displacement(ddstress_relax r, void* u, void* stream);
+
+ddstress_status ddstress_relax_get_info(ddstress_relax r, ddstress_relax_info* info);
+
+/* Free the plan (synchronises the device first). NULL is accepted. */
+ddstress_status ddstress_relax_destroy(ddstress_relax r);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char* ddstress_last_error(void);
 

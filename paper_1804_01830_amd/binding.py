@@ -20,7 +20,10 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STAT
 EXPORTS = ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
            "ddstress_set_density", "ddstress_stress",
            "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times",
-           "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_last_error", "ddstress_version")
+           "ddstress_plan_destroy", "ddstress_kernel_realspace",
+           "ddstress_relax_create", "ddstress_relax_set_load", "ddstress_relax_iterate", "ddstress_relax_update_norm",
+           "ddstress_relax_stress", "ddstress_relax_displacement", "ddstress_relax_get_info", "ddstress_relax_destroy",
+           "ddstress_last_error", "ddstress_version")
 PASS_NAMES = ("x_r2c", "y_fwd", "z_fused", "y_inv", "x_c2r")
 
 
@@ -47,6 +50,16 @@ class Info(ctypes.Structure):
                 ("mirror_z", ctypes.c_int32),
                 ("cached_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t),
                 ("kernel_real_max", ctypes.c_double), ("kernel_imag_max", ctypes.c_double)]
+
+
+class RelaxDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("d", ctypes.c_double * 3), ("mu", ctypes.c_double),
+                ("nu", ctypes.c_double), ("precision", ctypes.c_int32), ("dt", ctypes.c_double)]
+
+
+class RelaxInfo(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("A", ctypes.c_double), ("B", ctypes.c_double),
+                ("work_bytes", ctypes.c_size_t), ("steps", ctypes.c_int64)]
 
 
 class DDStressError(RuntimeError):
@@ -83,6 +96,17 @@ def load(path=LIB_PATH):
     lib.ddstress_plan_share.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
     lib.ddstress_stress_batch.argtypes = [P, P, P, ctypes.c_int32, P]
     lib.ddstress_plan_get_pass_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.ddstress_relax_create.argtypes = [ctypes.POINTER(RelaxDesc), ctypes.POINTER(P)]
+    lib.ddstress_relax_set_load.argtypes = [P, P, P]
+    lib.ddstress_relax_iterate.argtypes = [P, ctypes.c_int32, P]
+    lib.ddstress_relax_update_norm.argtypes = [P, ctypes.POINTER(ctypes.c_double), P]
+    lib.ddstress_relax_stress.argtypes = [P, P, P, P]
+    lib.ddstress_relax_displacement.argtypes = [P, P, P]
+    lib.ddstress_relax_get_info.argtypes = [P, ctypes.POINTER(RelaxInfo)]
+    lib.ddstress_relax_destroy.argtypes = [P]
+    for name in EXPORTS:
+        if name.startswith("ddstress_relax"):
+            getattr(lib, name).restype = ctypes.c_int
     for name in ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
                  "ddstress_set_density", "ddstress_stress",
                  "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_graph", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times",
@@ -233,6 +257,83 @@ class Plan:
     def close(self):
         if self._h:
             check(load().ddstress_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Relax:
+    """Owns one ``ddstress_relax`` plan: relaxation of a dislocation stress
+    field under free top and bottom surfaces, periodic in x and y. Tensors are
+    torch CUDA tensors of the plan precision."""
+
+    def __init__(self, n, d, mu, nu, precision=64, dt=0.0):
+        self.desc = RelaxDesc()
+        for a in range(3):
+            self.desc.n[a] = int(n[a])
+            self.desc.d[a] = float(d[a])
+        self.desc.mu = float(mu)
+        self.desc.nu = float(nu)
+        self.desc.precision = int(precision)
+        self.desc.dt = float(dt)
+        self.n = tuple(int(v) for v in n)
+        self.precision = int(precision)
+        self._h = ctypes.c_void_p()
+        check(load().ddstress_relax_create(ctypes.byref(self.desc), ctypes.byref(self._h)))
+
+    def _check(self, t, shape):
+        import torch
+        dt = torch.float32 if self.precision == 32 else torch.float64
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or tuple(t.shape) != shape:
+            raise ValueError(f"expected a contiguous CUDA {dt} tensor of shape {shape}, got {tuple(t.shape)} "
+                             f"{t.dtype} on {t.device}")
+
+    def _sigma_shape(self):
+        nx, ny, nz = self.n
+        return (6, nz, ny, nx)
+
+    def set_load(self, sigma_dis, stream=None):
+        self._check(sigma_dis, self._sigma_shape())
+        check(load().ddstress_relax_set_load(self._h, ctypes.c_void_p(sigma_dis.data_ptr()), _stream_handle(stream)))
+
+    def iterate(self, n_steps, stream=None):
+        check(load().ddstress_relax_iterate(self._h, int(n_steps), _stream_handle(stream)))
+
+    def update_norm(self, stream=None):
+        out = ctypes.c_double()
+        check(load().ddstress_relax_update_norm(self._h, ctypes.byref(out), _stream_handle(stream)))
+        return out.value
+
+    def stress(self, sigma_dis, out=None, stream=None):
+        import torch
+        self._check(sigma_dis, self._sigma_shape())
+        if out is None:
+            out = torch.empty_like(sigma_dis)
+        self._check(out, self._sigma_shape())
+        check(load().ddstress_relax_stress(self._h, ctypes.c_void_p(sigma_dis.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
+    def displacement(self, stream=None):
+        import torch
+        nx, ny, nz = self.n
+        dt = torch.float32 if self.precision == 32 else torch.float64
+        u = torch.empty((3, nz + 2, ny, nx), dtype=dt, device="cuda")
+        check(load().ddstress_relax_displacement(self._h, ctypes.c_void_p(u.data_ptr()), _stream_handle(stream)))
+        return u
+
+    def info(self):
+        info = RelaxInfo()
+        check(load().ddstress_relax_get_info(self._h, ctypes.byref(info)))
+        return info
+
+    def close(self):
+        if self._h:
+            check(load().ddstress_relax_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -17,6 +17,8 @@ namespace {
 thread_local std::string g_last_error;
 }
 
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
 [[noreturn]] void fail(ddstress_status s, const std::string& msg) { throw Error{s, msg}; }
 
 void check_hip(hipError_t e, const char* what) {
@@ -28,52 +30,6 @@ void check_hip(hipError_t e, const char* what) {
 }
 
 namespace {
-
-template <class F>
-ddstress_status guarded(F&& f) {
-    try {
-        f();
-        return DDSTRESS_OK;
-    } catch (const Error& e) {
-        g_last_error = e.msg;
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        g_last_error = "host allocation failed";
-        return DDSTRESS_E_NOMEM;
-    } catch (...) {
-        g_last_error = "unexpected internal error";
-        return DDSTRESS_E_DEVICE;
-    }
-}
-
-// Device buffer that frees itself.
-struct DevBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-    DevBuf() = default;
-    DevBuf(const DevBuf&) = delete;
-    DevBuf& operator=(const DevBuf&) = delete;
-    ~DevBuf() { release(); }
-    void alloc(size_t n, const char* what) {
-        release();
-        if (n == 0) n = 256;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            fail(DDSTRESS_E_NOMEM, std::string("device allocation failed: ") + what + " (" +
-                                       std::to_string(n) + " bytes)");
-        }
-        bytes = n;
-    }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    template <typename T>
-    T* as() const { return static_cast<T*>(p); }
-};
 
 // Shape facts derived from a descriptor.
 struct Shape {

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <new>
 #include <string>
 
 #include "../../include/ddstress.h"
@@ -19,6 +20,55 @@ struct Error {
 };
 [[noreturn]] void fail(ddstress_status s, const std::string& msg);
 void check_hip(hipError_t e, const char* what);
+void set_last_error(const std::string& msg);
+
+// Runs f and turns what it throws into a status (the message is kept for
+// ddstress_last_error).
+template <class F>
+ddstress_status guarded(F&& f) {
+    try {
+        f();
+        return DDSTRESS_OK;
+    } catch (const Error& e) {
+        set_last_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return DDSTRESS_E_NOMEM;
+    } catch (...) {
+        set_last_error("unexpected internal error");
+        return DDSTRESS_E_DEVICE;
+    }
+}
+
+// Device buffer that frees itself.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(size_t n, const char* what) {
+        release();
+        if (n == 0) n = 256;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(DDSTRESS_E_NOMEM, std::string("device allocation failed: ") + what + " (" +
+                                       std::to_string(n) + " bytes)");
+        }
+        bytes = n;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int next_pow2(int v) {

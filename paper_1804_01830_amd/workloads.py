@@ -138,3 +138,28 @@ def random_field(n, n_lines=1, batch=1, seed=0, d=(1.0, 1.0, 1.0), mu=1.0, nu=0.
     rho = rng.uniform(-1.0, 1.0, size=(batch, 3 * len(lines), nz, ny, nx))
     return dict(name=f"random-{nx}x{ny}x{nz}-L{len(lines)}-B{batch}", n=(nx, ny, nz), d=tuple(d),
                 mu=mu, nu=nu, lines=np.asarray(lines, dtype=np.float64), rho=rho)
+
+
+def random_stress(n, seed=0, d=(1.0, 1.0, 1.0), mu=1.0, nu=0.3, smooth=False):
+    """A load for the free-surface relaxation: six Voigt stress components on
+    an Nx x Ny x Nz node grid, Uniform(-1, 1) per node, or with ``smooth`` a
+    sum of four random in-plane Fourier modes (periodic in x and y) times a
+    random quadratic in z."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = n
+    if not smooth:
+        sig = rng.uniform(-1.0, 1.0, size=(6, nz, ny, nx))
+    else:
+        x = np.arange(nx) / nx
+        y = np.arange(ny) / ny
+        z = np.arange(nz) / max(1, nz - 1)
+        sig = np.zeros((6, nz, ny, nx))
+        for v in range(6):
+            for _ in range(4):
+                kx, ky = rng.integers(0, 4, size=2)
+                ph = rng.uniform(0.0, 2.0 * np.pi)
+                plane = np.cos(2.0 * np.pi * (kx * x[None, :] + ky * y[:, None]) + ph)
+                c = rng.uniform(-1.0, 1.0, size=3)
+                prof = c[0] + c[1] * z + c[2] * z * z
+                sig[v] += prof[:, None, None] * plane[None]
+    return dict(name=f"stress-{nx}x{ny}x{nz}", n=(nx, ny, nz), d=tuple(d), mu=mu, nu=nu, sigma=sig)

@@ -97,3 +97,17 @@ def test_tuning_key_separates_periodic_plans():
     b = Tn.shape_key(_desc(n=(16, 16, 4), periodic=(True, True)), "gfx950-256cu")
     c = Tn.shape_key(_desc(n=(16, 16, 4), periodic=(False, True)), "gfx950-256cu")
     assert len({a, b, c}) == 3 and "pbc" not in a and "pbcxy" in b and "pbcy" in c
+
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=(8, 8, 2)), B.E_INVALID), (dict(n=(0, 8, 4)), B.E_INVALID), (dict(precision=16), B.E_INVALID),
+    (dict(nu=0.5), B.E_INVALID), (dict(mu=-1.0), B.E_INVALID), (dict(dt=-1e-3), B.E_INVALID),
+    (dict(d=(1.0, 0.0, 1.0)), B.E_INVALID), (dict(n=(8, 8, 5000)), B.E_UNSUPPORTED),
+])
+def test_relaxation_descriptors_are_validated_before_any_device_work(kw, status):
+    base = dict(n=(8, 8, 4), d=(1.0, 1.0, 1.0), mu=1.0, nu=0.3, precision=64, dt=0.0)
+    base.update(kw)
+    with pytest.raises(B.DDStressError) as e:
+        B.Relax(**base)
+    assert e.value.status == status
