@@ -267,6 +267,92 @@ def serve_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def relax_step_bytes(n, elem):
+    """Algorithmic HBM bytes of one explicit relaxation step: every node reads
+    its three displacement components and three force components and writes
+    three displacement components (neighbours come from caches); the two
+    ghost layers add 3 * 2 * Nx * Ny writes and their reads."""
+    nx, ny, nz = n
+    return elem * (9 * nx * ny * nz + 2 * 3 * 2 * nx * ny)
+
+
+def relax_bench(args):
+    """Free-surface relaxation (Sec. 5) of the periodic layer's dislocation
+    stress: the stress plan evaluates sigma^dis once, then K explicit steps
+    are timed; also the steps needed to bring the update norm below 1e-6 of
+    its first value on the same load."""
+    import numpy as np
+    import torch
+    from paper_1804_01830_amd import binding as Bd
+    torch.cuda.set_device(0)
+    w = make_workload("poly-pbc-256")
+    nx, ny, nz = w["n"]
+    nodes = nx * ny * nz
+    res = {}
+    for prec in (32, 64):
+        dt = torch.float32 if prec == 32 else torch.float64
+        desc = Bd.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=prec, periodic=(True, True))
+        plan = Bd.Plan(desc)
+        rho = torch.from_numpy(w["rho"]).to("cuda", dtype=dt).contiguous()
+        plan.set_density(rho)
+        sig = plan.new_output()
+        plan.stress(sig)
+        sig = sig[0].contiguous()
+        torch.cuda.synchronize()
+        plan.close()
+        r = Bd.Relax(w["n"], w["d"], w["mu"], w["nu"], precision=prec)
+        r.set_load(sig)
+        r.iterate(args.warmup)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        steps = args.relax_steps
+        t0.record(stream)
+        r.iterate(steps)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        # convergence on the same load, from u = 0
+        r.set_load(sig)
+        first = r.update_norm()
+        conv, taken = None, 0
+        while taken < args.relax_max_steps:
+            r.iterate(1000)
+            taken += 1000
+            nrm = r.update_norm()
+            if nrm <= 1e-6 * first:
+                conv = taken
+                break
+        info = r.info()
+        r.close()
+        res[prec] = dict(ms=ms, steps=steps, dt=info.dt, first=first, last=nrm, conv=conv, taken=taken)
+        print(f"[relax] precision {prec}: {ms / steps * 1e3:.2f} us/step, update norm {first:.3e} -> {nrm:.3e} "
+              f"after {taken} steps", file=sys.stderr, flush=True)
+    r32, r64 = res[32], res[64]
+    per32 = r32["ms"] / r32["steps"] * 1e-3
+    per64 = r64["ms"] / r64["steps"] * 1e-3
+    b32 = relax_step_bytes(w["n"], 4)
+    line = {
+        "metric": "free-surface relaxation: node-steps/s (explicit Navier-Cauchy steps, Eq. 17)",
+        "value": round(nodes / per32, 1), "unit": "node-steps/s", "n_gpus": 1, "steps": r32["steps"],
+        "warmup": args.warmup, "ms_per_step": round(per32 * 1e3, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded)",
+        "config": {"workload": "relax-" + w["name"], "grid": [nx, ny, nz], "cell": list(w["d"]), "nu": w["nu"],
+                   "load": "dislocation stress of the periodic layer (stress plan, 15 shells)",
+                   "boundary": "periodic x, y; traction-free top and bottom"},
+        "fp64": {"value": round(nodes / per64, 1), "ms_per_step": round(per64 * 1e3, 5)},
+        "roofline": {"bound": "hbm", "achieved": round(b32 / per32 / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(b32 / per32 / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_relax_step + k_relax_ghost (one step; events around K steps)",
+                     "algorithmic_bytes_per_launch": int(b32)},
+        "convergence": {str(p): {"dt": res[p]["dt"], "update_norm_first": res[p]["first"],
+                                 "update_norm_last": res[p]["last"], "steps_to_1e-6": res[p]["conv"],
+                                 "steps_run": res[p]["taken"]} for p in (32, 64)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +370,10 @@ def main():
                     help="after the run, copy a device buffer of this many MiB once (a plain copy kernel of "
                          "known size, for scaling hardware traffic counters)")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
+    ap.add_argument("--relax", action="store_true",
+                    help="run the free-surface relaxation benchmark on the periodic layer instead")
+    ap.add_argument("--relax-steps", type=int, default=2000)
+    ap.add_argument("--relax-max-steps", type=int, default=100000)
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-pool", type=int, default=4)
     ap.add_argument("--serve-batch", type=int, default=4)
@@ -295,6 +385,9 @@ def main():
         sys.exit(2)
     if args.serve:
         serve_bench(args)
+        return
+    if args.relax:
+        relax_bench(args)
         return
 
     w = make_workload(args.workload, args.batch)
