@@ -263,6 +263,17 @@ ddstress_status ddstress_plan_destroy(ddstress_plan plan);
 ddstress_status ddstress_kernel_realspace(const ddstress_desc* desc, int32_t line, double* out,
                                           void* stream);
 
+/* In-plane statistics (Sec. 6, Eq. 20): for each realisation b, stress
+ * component v and layer k,
+ *     out[b][v][k] = (1 / (Nx Ny)) sum_{i,j} sigma[b][v][k][j][i]^2,
+ * the mean square over the plane (as printed, without subtracting the plane
+ * mean). sigma: device buffer [nbatch][6][Nz][Ny][Nx] of float
+ * (precision 32) or double (64), e.g. the output of ddstress_stress; out:
+ * device buffer of nbatch * 6 * Nz doubles. Accumulated in FP64 in a fixed
+ * order (the same input gives the same bits). Enqueued on `stream`. */
+ddstress_status ddstress_plane_mean_square(const void* sigma, int32_t precision, const int32_t n[3],
+                                           int32_t nbatch, double* out, void* stream);
+
 /* ---- Relaxation under free surfaces (Sec. 5, Eq. 14-18) --------------------
  *
  * A film of Nx x Ny x Nz nodes (cell centres), periodic in x and y (Eq. 16a),

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STAT
 EXPORTS = ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
            "ddstress_set_density", "ddstress_stress",
            "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times",
-           "ddstress_plan_destroy", "ddstress_kernel_realspace",
+           "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_plane_mean_square",
            "ddstress_relax_create", "ddstress_relax_set_load", "ddstress_relax_iterate", "ddstress_relax_update_norm",
            "ddstress_relax_stress", "ddstress_relax_displacement", "ddstress_relax_get_info", "ddstress_relax_destroy",
            "ddstress_last_error", "ddstress_version")
@@ -96,6 +96,8 @@ def load(path=LIB_PATH):
     lib.ddstress_plan_share.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
     lib.ddstress_stress_batch.argtypes = [P, P, P, ctypes.c_int32, P]
     lib.ddstress_plan_get_pass_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.ddstress_plane_mean_square.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, P, P]
+    lib.ddstress_plane_mean_square.restype = ctypes.c_int
     lib.ddstress_relax_create.argtypes = [ctypes.POINTER(RelaxDesc), ctypes.POINTER(P)]
     lib.ddstress_relax_set_load.argtypes = [P, P, P]
     lib.ddstress_relax_iterate.argtypes = [P, ctypes.c_int32, P]
@@ -341,6 +343,24 @@ class Relax:
             self.close()
         except Exception:
             pass
+
+
+def plane_mean_square(sigma, out=None, stream=None):
+    """Eq. (20): the mean square over each layer plane of a CUDA tensor
+    (nb, 6, Nz, Ny, Nx) (float32 or float64); returns (nb, 6, Nz) float64."""
+    import torch
+    if not sigma.is_cuda or sigma.dim() != 5 or sigma.shape[1] != 6 or not sigma.is_contiguous() \
+            or sigma.dtype not in (torch.float32, torch.float64):
+        raise ValueError(f"expected a contiguous CUDA float tensor (nb, 6, Nz, Ny, Nx), got {tuple(sigma.shape)} "
+                         f"{sigma.dtype} on {sigma.device}")
+    nb, _, nz, ny, nx = sigma.shape
+    if out is None:
+        out = torch.empty((nb, 6, nz), dtype=torch.float64, device=sigma.device)
+    n = (ctypes.c_int32 * 3)(nx, ny, nz)
+    check(load().ddstress_plane_mean_square(ctypes.c_void_p(sigma.data_ptr()), 32 if sigma.dtype == torch.float32
+                                            else 64, n, int(nb), ctypes.c_void_p(out.data_ptr()),
+                                            _stream_handle(stream)))
+    return out
 
 
 def autotune(desc, stream=None):

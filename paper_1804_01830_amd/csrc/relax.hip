@@ -13,6 +13,7 @@
 // Kernels, all HBM-bound stencils: k_relax_load (f, surface terms, u = 0),
 // k_relax_step (one explicit step into the other state buffer, or the max of
 // |update| / dt), k_relax_ghost (both ghost layers), k_relax_stress.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -24,6 +25,17 @@ namespace dds {
 namespace {
 
 constexpr int kRelaxBX = 64, kRelaxBY = 4;
+// Tile of the z-marching step and the number of blocks its z chunks aim at.
+#ifndef DDS_RELAX_TX
+#define DDS_RELAX_TX 64
+#endif
+#ifndef DDS_RELAX_TY
+#define DDS_RELAX_TY 8
+#endif
+#ifndef DDS_RELAX_BLOCKS
+#define DDS_RELAX_BLOCKS 1024
+#endif
+constexpr int kRelaxBlocks = DDS_RELAX_BLOCKS;
 constexpr int kRelaxMaxN = 4096;
 
 template <typename T>
@@ -114,16 +126,12 @@ __global__ void __launch_bounds__(kRelaxBX* kRelaxBY)
     }
 }
 
-// Ghost layers from the real layers (Eq. 16c on both surfaces). One thread
-// per (i, j); blockIdx.z = 0 bottom, 1 top.
+// Ghost values at column (i, j) of the bottom (top = 0) or top surface from
+// the real layers of u (Eq. 16c solved for the ghost value, Eq. 18b).
 template <typename T>
-__global__ void __launch_bounds__(kRelaxBX* kRelaxBY)
-    k_relax_ghost(T* __restrict__ u, const T* __restrict__ phi, RelaxGeom<T> g) {
-    const int i = blockIdx.x * kRelaxBX + threadIdx.x;
-    const int j = blockIdx.y * kRelaxBY + threadIdx.y;
-    if (i >= g.nx || j >= g.ny) return;
-    const int top = blockIdx.z;
-    const int s = top ? g.nz : 1, inner = top ? g.nz - 1 : 2, ghost = top ? g.nz + 1 : 0;
+__device__ __forceinline__ void ghost_value(const T* __restrict__ u, const T* __restrict__ phi, const RelaxGeom<T>& g,
+                                            int top, int i, int j, T out[3]) {
+    const int s = top ? g.nz : 1, inner = top ? g.nz - 1 : 2;
     const int ip = nxt(i, g.nx), im = prv(i, g.nx), jp = nxt(j, g.ny), jm = prv(j, g.ny);
     const int64_t r0 = (int64_t)j * g.nx, rp = (int64_t)jp * g.nx, rm = (int64_t)jm * g.nx;
     const T* ux = u;
@@ -135,16 +143,134 @@ __global__ void __launch_bounds__(kRelaxBX* kRelaxBY)
     const T dxy = (ux[ls + r0 + ip] - ux[ls + r0 + im]) * g.hx + (uy[ls + rp + i] - uy[ls + rm + i]) * g.hy;
     const int64_t q = (int64_t)top * 3 * g.plane + r0 + i;
     const T pxz = phi[q], pyz = phi[q + g.plane], pzz = phi[q + 2 * g.plane];
-    const int64_t o = (int64_t)ghost * g.plane + r0 + i;
     if (!top) {
-        u[o] = ux[li + r0 + i] + g.twodz * (gx - T(2) * pxz);
-        u[g.cstride + o] = uy[li + r0 + i] + g.twodz * (gy - T(2) * pyz);
-        u[2 * g.cstride + o] = uz[li + r0 + i] - g.twodz * (pzz - g.nu * dxy) * g.inv1mnu;
+        out[0] = ux[li + r0 + i] + g.twodz * (gx - T(2) * pxz);
+        out[1] = uy[li + r0 + i] + g.twodz * (gy - T(2) * pyz);
+        out[2] = uz[li + r0 + i] - g.twodz * (pzz - g.nu * dxy) * g.inv1mnu;
     } else {
-        u[o] = ux[li + r0 + i] + g.twodz * (T(2) * pxz - gx);
-        u[g.cstride + o] = uy[li + r0 + i] + g.twodz * (T(2) * pyz - gy);
-        u[2 * g.cstride + o] = uz[li + r0 + i] + g.twodz * (pzz - g.nu * dxy) * g.inv1mnu;
+        out[0] = ux[li + r0 + i] + g.twodz * (T(2) * pxz - gx);
+        out[1] = uy[li + r0 + i] + g.twodz * (T(2) * pyz - gy);
+        out[2] = uz[li + r0 + i] + g.twodz * (pzz - g.nu * dxy) * g.inv1mnu;
     }
+}
+
+// One explicit step, marching along z: a block owns a TX x TY tile of
+// columns and a chunk of node layers; the three displacement planes the
+// stencil touches (layers k - 1, k, k + 1, three components, one halo cell
+// on each side, periodic wrap) live in LDS in a rotating set of three slots,
+// and the next plane is fetched into registers while the current layer is
+// computed. Each displacement value is read from memory once per chunk
+// (plus halos and the two planes that chunks share); the blocks of one tile
+// take consecutive logical indices, which xcd_block keeps on one XCD. The
+// ghost planes are read like the others (a ghost pass follows every step:
+// evaluating them in the surface blocks instead puts their dependent loads
+// on the critical path and was slower).
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(TX* TY)
+    k_relax_march(const T* __restrict__ u, T* __restrict__ un, const T* __restrict__ f, RelaxGeom<T> g, int tiles_x,
+                  int nchunks, int kc) {
+    constexpr int W = TX + 2, H = TY + 2, PL = W * H;           // plane tile with halo
+    constexpr int NT = TX * TY, PER = (PL + NT - 1) / NT;       // loads per thread per component
+    __shared__ T lds[3][3][PL];                                 // [slot][component][tile]
+    const int nb = gridDim.x;
+    const int lb = xcd_block(blockIdx.x, nb);
+    const int chunk = lb % nchunks, tile = lb / nchunks;
+    const int i0 = (tile % tiles_x) * TX, j0 = (tile / tiles_x) * TY;
+    const int k0 = chunk * kc;
+    const int k1 = min(g.nz, k0 + kc);
+    if (k0 >= k1) return;                                       // uniform per block
+    const int t = threadIdx.x, tx = t % TX, ty = t / TX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool ok = i < g.nx && j < g.ny;
+    // global offsets (within one layer) of this thread's share of the halo tile
+    int64_t off[PER];
+    int slot_e[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = t + q * NT;
+        slot_e[q] = e < PL ? e : -1;
+        const int ex = e % W, ey = e / W;
+        int gx = (i0 + ex - 1) % g.nx, gy = (j0 + ey - 1) % g.ny;
+        if (gx < 0) gx += g.nx;
+        if (gy < 0) gy += g.ny;
+        off[q] = (int64_t)gy * g.nx + gx;
+    }
+    T pre[3][PER];
+    auto fetch = [&](int layer) {
+        const int64_t lo = (int64_t)layer * g.plane;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (slot_e[q] >= 0) pre[c][q] = u[c * g.cstride + lo + off[q]];
+    };
+    auto store = [&](int layer) {
+        const int sl = layer % 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (slot_e[q] >= 0) lds[sl][c][slot_e[q]] = pre[c][q];
+    };
+    const int ctr = (ty + 1) * W + tx + 1;
+    auto compute = [&](int k) {
+        if (!ok) return;
+        const int L = k + 1;
+        const int sd = (L - 1) % 3, sc = L % 3, su = (L + 1) % 3;
+        T dxx[3], dyy[3], dzz[3], dxy[3], dxz[3], dyz[3], u0[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T* lz = lds[sc][c];
+            const T* lu = lds[su][c];
+            const T* ld = lds[sd][c];
+            const T c0 = lz[ctr];
+            u0[c] = c0;
+            dxx[c] = (lz[ctr + 1] - T(2) * c0 + lz[ctr - 1]) * g.qx;
+            dyy[c] = (lz[ctr + W] - T(2) * c0 + lz[ctr - W]) * g.qy;
+            dzz[c] = (lu[ctr] - T(2) * c0 + ld[ctr]) * g.qz;
+            dxy[c] = ((lz[ctr + W + 1] - lz[ctr + W - 1]) * g.hx - (lz[ctr - W + 1] - lz[ctr - W - 1]) * g.hx) * g.hy;
+            dxz[c] = ((lu[ctr + 1] - lu[ctr - 1]) * g.hx - (ld[ctr + 1] - ld[ctr - 1]) * g.hx) * g.hz;
+            dyz[c] = ((lu[ctr + W] - lu[ctr - W]) * g.hy - (ld[ctr + W] - ld[ctr - W]) * g.hy) * g.hz;
+        }
+        const T gd[3] = {dxx[0] + dxy[1] + dxz[2], dxy[0] + dyy[1] + dyz[2], dxz[0] + dyz[1] + dzz[2]};
+        const int64_t n = (int64_t)k * g.plane + (int64_t)j * g.nx + i;
+        const int64_t o = n + g.plane;                          // the same node in the displacement layout
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T lap = dxx[a] + dyy[a] + dzz[a];
+            const T v = (g.A - g.B) * gd[a] + g.B * lap + f[a * g.fstride + n];
+            un[a * g.cstride + o] = u0[a] + g.dt * v;
+        }
+    };
+    fetch(k0);
+    store(k0);
+    fetch(k0 + 1);
+    store(k0 + 1);
+    fetch(k0 + 2);
+    for (int k = k0; k < k1; ++k) {
+        const int L = k + 1;                                    // u layer of node layer k
+        store(L + 1);
+        __syncthreads();
+        if (k + 1 < k1) fetch(L + 2);                           // overlaps the arithmetic below
+        compute(k);
+        __syncthreads();                                        // slot (L - 1) % 3 is refilled next
+    }
+}
+
+// Ghost layers from the real layers (Eq. 16c on both surfaces). One thread
+// per (i, j); blockIdx.z = 0 bottom, 1 top.
+template <typename T>
+__global__ void __launch_bounds__(kRelaxBX* kRelaxBY)
+    k_relax_ghost(T* __restrict__ u, const T* __restrict__ phi, RelaxGeom<T> g) {
+    const int i = blockIdx.x * kRelaxBX + threadIdx.x;
+    const int j = blockIdx.y * kRelaxBY + threadIdx.y;
+    if (i >= g.nx || j >= g.ny) return;
+    const int top = blockIdx.z;
+    T v[3];
+    ghost_value(u, phi, g, top, i, j, v);
+    const int64_t o = (int64_t)(top ? g.nz + 1 : 0) * g.plane + (int64_t)j * g.nx + i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c * g.cstride + o] = v[c];
 }
 
 // f = div sigma^dis on the nodes, the surface terms phi [2][3][Ny][Nx] and
@@ -274,6 +400,7 @@ struct ddstress_relax_s {
     DevBuf u[2], f, phi, red;
     int cur = 0;
     bool loaded = false;
+    bool march = true;      // z-marching step kernel (false: one thread per node, no LDS)
     int64_t steps = 0;
 
     int64_t nodes() const { return (int64_t)desc.n[0] * desc.n[1] * desc.n[2]; }
@@ -297,11 +424,24 @@ struct ddstress_relax_s {
     template <typename T>
     void iterate(int n, hipStream_t st) {
         const RelaxGeom<T> g = make_geom<T>(desc, dt, A, B);
+        // z-marching tiles of TX x TY columns; z chunks so that about kRelaxBlocks blocks run
+        constexpr int TX = DDS_RELAX_TX, TY = DDS_RELAX_TY;
+        const int tiles_x = (desc.n[0] + TX - 1) / TX, tiles_y = (desc.n[1] + TY - 1) / TY;
+        const int tiles = tiles_x * tiles_y;
+        int nchunks = std::max(1, std::min(desc.n[2], (kRelaxBlocks + tiles - 1) / tiles));
+        const int kc = (desc.n[2] + nchunks - 1) / nchunks;
+        nchunks = (desc.n[2] + kc - 1) / kc;
+        const unsigned blocks = (unsigned)(tiles * nchunks);
         for (int s = 0; s < n; ++s) {
             T* a = u[cur].as<T>();
             T* b = u[cur ^ 1].as<T>();
-            hipLaunchKernelGGL((k_relax_step<T, 0>), grid(desc.n[2]), dim3(kRelaxBX, kRelaxBY), 0, st, a, b, f.as<T>(),
-                               g, nullptr);
+            if (march) {
+                hipLaunchKernelGGL((k_relax_march<T, TX, TY>), dim3(blocks), dim3(TX * TY), 0, st, a, b, f.as<T>(), g,
+                                   tiles_x, nchunks, kc);
+            } else {
+                hipLaunchKernelGGL((k_relax_step<T, 0>), grid(desc.n[2]), dim3(kRelaxBX, kRelaxBY), 0, st, a, b,
+                                   f.as<T>(), g, nullptr);
+            }
             check_hip(hipGetLastError(), "relaxation step launch");
             hipLaunchKernelGGL((k_relax_ghost<T>), grid(2), dim3(kRelaxBX, kRelaxBY), 0, st, b, phi.as<T>(), g);
             check_hip(hipGetLastError(), "relaxation ghost launch");

@@ -1,0 +1,68 @@
+// In-plane mean square of each stress component at each height (Sec. 6,
+// Eq. 20): one block per (realisation, component, layer) plane, FP64
+// accumulation in a fixed order (four independent partial sums per thread,
+// then a tree over the block), so the result does not depend on anything
+// but the input. Reads the stress once: an HBM-bound reduction.
+#include "ddstress_internal.hpp"
+
+namespace dds {
+
+namespace {
+
+constexpr int kStatThreads = 512;
+
+template <typename T>
+__global__ void __launch_bounds__(kStatThreads)
+    k_plane_ms(const T* __restrict__ sigma, int64_t plane, double inv_plane, double* __restrict__ out) {
+    const T* p = sigma + (int64_t)blockIdx.x * plane;
+    const int t = threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t e = t;
+    for (; e + 3 * kStatThreads < plane; e += 4 * kStatThreads) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = (double)p[e + q * kStatThreads];
+            acc[q] += v * v;
+        }
+    }
+    for (int q = 0; e < plane; e += kStatThreads, ++q) {
+        const double v = (double)p[e];
+        acc[q & 3] += v * v;
+    }
+    __shared__ double red[kStatThreads];
+    red[t] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    for (int w = kStatThreads / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[blockIdx.x] = red[0] * inv_plane;
+}
+
+}  // namespace
+}  // namespace dds
+
+using namespace dds;
+
+extern "C" ddstress_status ddstress_plane_mean_square(const void* sigma, int32_t precision, const int32_t n[3],
+                                                      int32_t nbatch, double* out, void* stream) {
+    return guarded([&] {
+        if (!sigma || !out || !n) fail(DDSTRESS_E_INVALID, "NULL argument");
+        if (precision != 32 && precision != 64) fail(DDSTRESS_E_INVALID, "precision must be 32 or 64");
+        if (nbatch < 1) fail(DDSTRESS_E_INVALID, "nbatch must be >= 1");
+        for (int a = 0; a < 3; ++a)
+            if (n[a] < 1) fail(DDSTRESS_E_INVALID, "grid sizes must be >= 1");
+        const int64_t planes = (int64_t)nbatch * 6 * n[2];
+        if (planes > 0x7fffffff) fail(DDSTRESS_E_UNSUPPORTED, "too many planes");
+        const int64_t plane = (int64_t)n[0] * n[1];
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const double inv = 1.0 / (double)plane;
+        if (precision == 32)
+            hipLaunchKernelGGL((k_plane_ms<float>), dim3((unsigned)planes), dim3(kStatThreads), 0, st,
+                               static_cast<const float*>(sigma), plane, inv, out);
+        else
+            hipLaunchKernelGGL((k_plane_ms<double>), dim3((unsigned)planes), dim3(kStatThreads), 0, st,
+                               static_cast<const double*>(sigma), plane, inv, out);
+        check_hip(hipGetLastError(), "plane statistics launch");
+    });
+}

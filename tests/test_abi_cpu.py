@@ -111,3 +111,14 @@ def test_relaxation_descriptors_are_validated_before_any_device_work(kw, status)
     with pytest.raises(B.DDStressError) as e:
         B.Relax(**base)
     assert e.value.status == status
+
+
+def test_plane_statistics_arguments_are_validated_before_any_device_work():
+    import ctypes
+    lib = B.load()
+    n = (ctypes.c_int32 * 3)(8, 8, 4)
+    bad_n = (ctypes.c_int32 * 3)(8, 0, 4)
+    dummy = ctypes.c_void_p(16)                  # never dereferenced: validation fails first
+    for args in ((None, 32, n, 1, dummy), (dummy, 32, n, 1, None), (dummy, 16, n, 1, dummy),
+                 (dummy, 32, n, 0, dummy), (dummy, 64, bad_n, 1, dummy)):
+        assert lib.ddstress_plane_mean_square(*args, None) == B.E_INVALID
