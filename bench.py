@@ -434,8 +434,21 @@ def main():
             graph = dict(wall=gw, per=gper)
             hw, hper, hbytes = time_host_io(plan, rho, min(steps, 50), min(args.warmup, 5))
             host = dict(wall=hw, per=hper, bytes=hbytes, steps=min(steps, 50))
+        stats_ms = None
+        if prec == 32:
+            # Eq. (20) plane statistics of the stress just computed (one read of sigma)
+            stream = torch.cuda.current_stream()
+            ms_out = Bd.plane_mean_square(out)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(20):
+                Bd.plane_mean_square(out, ms_out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            stats_ms = e0.elapsed_time(e1) / 20
         info = plan.info()
         res[prec] = dict(plan=plan, info=info, wall=wall, per=per, passes=passes, calls=calls, steps=steps,
+                         stats_ms=stats_ms,
                          plan_s=plan_s, graph=graph, host=host, tune=Tn.to_dict(tune) if tune is not None else None,
                          out=out[0].double().cpu().numpy() if (B == 1 or plain_one) else None,
                          cells=Bp * nx * ny * nz)
@@ -500,6 +513,9 @@ def main():
                          "pcie_bytes_per_step": r32["host"]["bytes"],
                          "note": "density from and stress to pinned host memory; not the headline value"},
         "plan_build_s": {"fp32": round(r32["plan_s"], 3), "fp64": round(r64["plan_s"], 3)},
+        "plane_stats": {"what": "Eq. 20 mean square per plane of the FP32 stress (ddstress_plane_mean_square)",
+                        "ms": round(r32["stats_ms"], 5),
+                        "gbs": round(B * 6 * nx * ny * nz * 4 / (r32["stats_ms"] * 1e-3) / 1e9, 1)},
         "roofline": roofline,
         "plan_info": plan_info,
     }

@@ -30,10 +30,10 @@ constexpr int kRelaxBX = 64, kRelaxBY = 4;
 #define DDS_RELAX_TX 64
 #endif
 #ifndef DDS_RELAX_TY
-#define DDS_RELAX_TY 8
+#define DDS_RELAX_TY 16
 #endif
 #ifndef DDS_RELAX_BLOCKS
-#define DDS_RELAX_BLOCKS 1024
+#define DDS_RELAX_BLOCKS 512
 #endif
 constexpr int kRelaxBlocks = DDS_RELAX_BLOCKS;
 constexpr int kRelaxMaxN = 4096;
