@@ -344,7 +344,7 @@ def relax_bench(args):
         "fp64": {"value": round(nodes / per64, 1), "ms_per_step": round(per64 * 1e3, 5)},
         "roofline": {"bound": "hbm", "achieved": round(b32 / per32 / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(b32 / per32 / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_relax_step + k_relax_ghost (one step; events around K steps)",
+                     "kernel": "k_relax_march + k_relax_ghost (one step; events around K steps)",
                      "algorithmic_bytes_per_launch": int(b32)},
         "convergence": {str(p): {"dt": res[p]["dt"], "update_norm_first": res[p]["first"],
                                  "update_norm_last": res[p]["last"], "steps_to_1e-6": res[p]["conv"],
