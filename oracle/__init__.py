@@ -27,6 +27,10 @@ What the oracle computes, in the paper's order:
 * ``periodic``: periodic boundary conditions in the layer plane (Sec. 4):
   the replica-shell interaction function Eq. (13), the periodic direct sum
   Eq. (12) and its library-FFT reference (circular convolution at the period).
+* ``stats``: the in-plane mean square of each stress component per height
+  (Eq. 20).
+* ``nye``: density channels in the axis basis for line directions that vary
+  from cell to cell (linearity in t, Sec. 2.1).
 * ``relax``: relaxation of the stress under free top and bottom surfaces
   (Sec. 5): force density Eq. (15), traction conditions Eq. (16c) on ghost
   layers Eq. (18b), explicit pseudo-time steps of Eq. (17), total stress.
