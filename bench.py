@@ -48,7 +48,30 @@ def make_workload(name, batch=1):
         return w
     if name == "sweep-64":
         return W.poly_sweep()
+    if name == "poly-lines-256":        # per-grain line directions, axis-basis channels (C = 9), periodic
+        w = W.poly_layer_lines()
+        w["periodic"] = (True, True)
+        return w
     raise SystemExit(f"unknown workload {name}")
+
+
+def device_density(w, nb, dt):
+    """The first nb densities on the device: the workload's channels, or for
+    per-cell line fields the axis-basis channels built by the library
+    (returns the tensor and the milliseconds of that conversion)."""
+    import torch
+    from paper_1804_01830_amd import binding as Bd
+    if "density" not in w:
+        return torch.from_numpy(w["rho"][:nb]).to("cuda", dtype=dt).contiguous(), None
+    n, t, b = (torch.from_numpy(w[k][:nb]).to("cuda", dtype=dt).contiguous() for k in ("density", "t", "b"))
+    rho = Bd.nye_density(n, t, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        Bd.nye_density(n, t, b, rho=rho)
+    e1.record()
+    torch.cuda.synchronize()
+    return rho, e0.elapsed_time(e1) / 10
 
 
 def z_pass_bytes(info, n, C, B, elem):
@@ -391,8 +414,13 @@ def main():
         return
 
     w = make_workload(args.workload, args.batch)
-    rho_np = w["rho"]
-    B, C = rho_np.shape[0], rho_np.shape[1]
+    if "density" in w:
+        import numpy as np
+        from paper_1804_01830_amd.binding import AXIS_LINES
+        w["lines"] = np.array(AXIS_LINES)
+        B, C = w["density"].shape[0], 9
+    else:
+        B, C = w["rho"].shape[0], w["rho"].shape[1]
     nx, ny, nz = w["n"]
     cells = B * nx * ny * nz
     plain_one = args.workload == "disk-mixed-128"     # FP64 plain: the single base grid
@@ -424,7 +452,7 @@ def main():
         plan = Bd.Plan(desc, tuning=tune)
         plan_s = time.perf_counter() - t
         dt = torch.float32 if prec == 32 else torch.float64
-        rho = torch.from_numpy(rho_np[:Bp]).to("cuda", dtype=dt).contiguous()
+        rho, nye_ms = device_density(w, Bp, dt)
         out = plan.new_output()
         steps = args.steps if prec == 32 else (args.fp64_steps or max(10, args.steps // 2))
         wall, per, passes, calls = time_path(plan, rho, out, steps, args.warmup, profile=True)
@@ -448,7 +476,7 @@ def main():
             stats_ms = e0.elapsed_time(e1) / 20
         info = plan.info()
         res[prec] = dict(plan=plan, info=info, wall=wall, per=per, passes=passes, calls=calls, steps=steps,
-                         stats_ms=stats_ms,
+                         stats_ms=stats_ms, nye_ms=nye_ms,
                          plan_s=plan_s, graph=graph, host=host, tune=Tn.to_dict(tune) if tune is not None else None,
                          out=out[0].double().cpu().numpy() if (B == 1 or plain_one) else None,
                          cells=Bp * nx * ny * nz)
@@ -519,6 +547,11 @@ def main():
         "roofline": roofline,
         "plan_info": plan_info,
     }
+    if r32["nye_ms"] is not None:
+        line["axis_basis_channels"] = {
+            "what": "rho[3l+g] = n t_l b_g from per-cell line fields (ddstress_nye_density), outside the step",
+            "ms": round(r32["nye_ms"], 5),
+            "gbs": round(B * (7 + 9) * nx * ny * nz * 4 / (r32["nye_ms"] * 1e-3) / 1e9, 1)}
     if base is not None:
         line["cpu_baseline"] = base
         line["error_vs_oracle"] = errors_at(tg, ref, r32["out"], r64["out"])

@@ -263,6 +263,22 @@ ddstress_status ddstress_plan_destroy(ddstress_plan plan);
 ddstress_status ddstress_kernel_realspace(const ddstress_desc* desc, int32_t line, double* out,
                                           void* stream);
 
+/* Density channels in the axis basis (the Nye tensor) for line directions
+ * that vary from cell to cell. Sec. 2.1 takes the stress of a volume element
+ * as linear in the line direction t; that is exact for infinitesimal
+ * segments, so a density n of lines along t with Burgers vector b acts, up to
+ * a near-field error that falls as (cell size / distance)^2, like the three
+ * axis densities n t_l. For a plan whose three line directions are e_x, e_y,
+ * e_z (C = 9), the channels are
+ *     rho[b][3 l + gamma] = n t_l b_gamma.
+ * n: [nbatch][Nz][Ny][Nx]; t, b: [nbatch][3][Nz][Ny][Nx] (t as given, its
+ * length is the caller's convention); rho: [nbatch][9][Nz][Ny][Nx]; device
+ * buffers of float (precision 32) or double (64). accumulate = 1 adds to rho
+ * (one call per dislocation family), 0 overwrites it. Enqueued on `stream`. */
+ddstress_status ddstress_nye_density(const void* n, const void* t, const void* b, int32_t precision,
+                                     const int32_t grid[3], int32_t nbatch, int32_t accumulate, void* rho,
+                                     void* stream);
+
 /* In-plane statistics (Sec. 6, Eq. 20): for each realisation b, stress
  * component v and layer k,
  *     out[b][v][k] = (1 / (Nx Ny)) sum_{i,j} sigma[b][v][k][j][i]^2,

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STAT
 EXPORTS = ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
            "ddstress_set_density", "ddstress_stress",
            "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times",
-           "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_plane_mean_square",
+           "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_nye_density", "ddstress_plane_mean_square",
            "ddstress_relax_create", "ddstress_relax_set_load", "ddstress_relax_iterate", "ddstress_relax_update_norm",
            "ddstress_relax_stress", "ddstress_relax_displacement", "ddstress_relax_get_info", "ddstress_relax_destroy",
            "ddstress_last_error", "ddstress_version")
@@ -96,6 +96,9 @@ def load(path=LIB_PATH):
     lib.ddstress_plan_share.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
     lib.ddstress_stress_batch.argtypes = [P, P, P, ctypes.c_int32, P]
     lib.ddstress_plan_get_pass_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.ddstress_nye_density.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                                         ctypes.c_int32, P, P]
+    lib.ddstress_nye_density.restype = ctypes.c_int
     lib.ddstress_plane_mean_square.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, P, P]
     lib.ddstress_plane_mean_square.restype = ctypes.c_int
     lib.ddstress_relax_create.argtypes = [ctypes.POINTER(RelaxDesc), ctypes.POINTER(P)]
@@ -343,6 +346,33 @@ class Relax:
             self.close()
         except Exception:
             pass
+
+
+AXIS_LINES = ((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0))
+
+
+def nye_density(n, t, b, rho=None, accumulate=False, stream=None):
+    """Axis-basis channels rho[:, 3 l + g] = n t_l b_g for a plan with the
+    line directions AXIS_LINES. n: (nb, Nz, Ny, Nx); t, b: (nb, 3, Nz, Ny, Nx);
+    CUDA tensors of one float dtype. Returns rho (nb, 9, Nz, Ny, Nx)."""
+    import torch
+    for x in (n, t, b):
+        if not x.is_cuda or not x.is_contiguous() or x.dtype != n.dtype or x.dtype not in (torch.float32,
+                                                                                            torch.float64):
+            raise ValueError("n, t, b must be contiguous CUDA tensors of one float dtype")
+    nb, nz, ny, nx = n.shape
+    if tuple(t.shape) != (nb, 3, nz, ny, nx) or tuple(b.shape) != (nb, 3, nz, ny, nx):
+        raise ValueError(f"t and b must have shape {(nb, 3, nz, ny, nx)}")
+    if rho is None:
+        rho = torch.empty((nb, 9, nz, ny, nx), dtype=n.dtype, device=n.device)
+    elif tuple(rho.shape) != (nb, 9, nz, ny, nx) or rho.dtype != n.dtype or not rho.is_contiguous():
+        raise ValueError(f"rho must be a contiguous {n.dtype} tensor of shape {(nb, 9, nz, ny, nx)}")
+    grid = (ctypes.c_int32 * 3)(nx, ny, nz)
+    check(load().ddstress_nye_density(ctypes.c_void_p(n.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                      ctypes.c_void_p(b.data_ptr()), 32 if n.dtype == torch.float32 else 64, grid,
+                                      int(nb), 1 if accumulate else 0, ctypes.c_void_p(rho.data_ptr()),
+                                      _stream_handle(stream)))
+    return rho
 
 
 def plane_mean_square(sigma, out=None, stream=None):

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libddstress.so")
 SOURCES = ["api.hip", "kernel_build.hip", "passes.hip", "z_serial_f32.hip", "z_serial_f64.hip",
-           "z_grouped_f32.hip", "z_grouped_f64.hip", "yx_fused.hip", "relax.hip", "stats.hip"]
+           "z_grouped_f32.hip", "z_grouped_f64.hip", "yx_fused.hip", "relax.hip", "stats.hip", "nye.hip"]
 ARCH = os.environ.get("DDSTRESS_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are switched off for all device code.

@@ -163,3 +163,34 @@ def random_stress(n, seed=0, d=(1.0, 1.0, 1.0), mu=1.0, nu=0.3, smooth=False):
                 prof = c[0] + c[1] * z + c[2] * z * z
                 sig[v] += prof[:, None, None] * plane[None]
     return dict(name=f"stress-{nx}x{ny}x{nz}", n=(nx, ny, nz), d=tuple(d), mu=mu, nu=nu, sigma=sig)
+
+
+def poly_layer_lines(nx=256, ny=256, nz=64, d=(1.0, 1.0, 2.0), grain=16.0, z_decay=8.0, mu=1.0, nu=0.2, seed=3,
+                     max_tilt_deg=30.0, periodic=True, batch_seeds=None):
+    """Columnar polycrystal layer whose dislocation lines vary from grain to
+    grain: per grain a line direction tilted from e_z by an angle uniform in
+    [0, max_tilt] at a uniform azimuth, and a Burgers vector (cos 60 i,
+    sin 60 i, 0), i ~ U{0..5}; line density n(z) = exp(-z / z_decay). Per-cell
+    fields n (nb, Nz, Ny, Nx), t and b (nb, 3, Nz, Ny, Nx) for the axis-basis
+    (Nye) channels."""
+    seeds = [seed] if batch_seeds is None else list(batch_seeds)
+    n_grains = max(1, int(round(nx * ny / float(grain) ** 2)))
+    z = np.arange(nz) * d[2]
+    prof = np.exp(-z / z_decay)
+    nb = len(seeds)
+    n = np.zeros((nb, nz, ny, nx))
+    t = np.zeros((nb, 3, nz, ny, nx))
+    b = np.zeros((nb, 3, nz, ny, nx))
+    for bi, sd in enumerate(seeds):
+        rng = np.random.default_rng(sd)
+        gmap = voronoi_grains(nx, ny, n_grains, rng, periodic)
+        tilt = np.radians(max_tilt_deg) * rng.uniform(0.0, 1.0, size=n_grains)
+        az = rng.uniform(0.0, 2.0 * np.pi, size=n_grains)
+        ang = np.radians(60.0) * rng.integers(0, 6, size=n_grains)
+        tg = np.stack([np.sin(tilt) * np.cos(az), np.sin(tilt) * np.sin(az), np.cos(tilt)])[:, gmap]
+        bg = np.stack([np.cos(ang), np.sin(ang), np.zeros(n_grains)])[:, gmap]
+        n[bi] = prof[:, None, None] * np.ones((ny, nx))[None]
+        t[bi] = tg[:, None]
+        b[bi] = bg[:, None]
+    name = f"poly-lines{'-pbc' if periodic else ''}-{nx}x{ny}x{nz}-g{grain:g}"
+    return dict(name=name, n=(nx, ny, nz), d=tuple(d), mu=mu, nu=nu, density=n, t=t, b=b)

@@ -161,3 +161,39 @@ def test_periodic_plans_refuse_non_power_of_two_axes():
     with pytest.raises(B.DDStressError) as e:
         B.Plan(desc)
     assert e.value.status == B.E_UNSUPPORTED
+
+
+def test_periodic_batches_graphs_and_shared_plans_are_bit_consistent():
+    """A periodic plan through the launch variants: partial batches, graph
+    replays (eager work between them) and a plan sharing its spectrum give
+    the bits of the direct full call."""
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w = W.random_field((32, 16, 4), n_lines=2, batch=3, seed=40, d=(1.0, 1.0, 2.0))
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=32, batch=3, periodic=(True, True),
+                       pbc_shells=2)
+    plan = B.Plan(desc)
+    assert tuple(plan.info().padded) == (32, 16, 8)
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32).contiguous()
+    ref = torch.empty((3, 6, 4, 16, 32), dtype=torch.float32, device="cuda")
+    plan.stress_batch(rho, ref, 3)
+    one = torch.empty((1, 6, 4, 16, 32), dtype=torch.float32, device="cuda")
+    plan.stress_batch(rho[:1], one, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(one, ref[:1])
+    plan.set_graph(True)
+    out = torch.empty_like(ref)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        plan.stress_batch(rho, out, 3)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {rep}"
+        assert torch.isfinite(torch.randn(1 << 18, device="cuda").sum())
+    plan.set_graph(False)
+    shared = plan.share(1)
+    for r in range(3):
+        shared.stress_batch(rho[r:r + 1].contiguous(), one, 1)
+        torch.cuda.synchronize()
+        assert torch.equal(one[0], ref[r])
+    shared.close()
+    plan.close()
