@@ -55,6 +55,37 @@ def make_workload(name, batch=1):
     raise SystemExit(f"unknown workload {name}")
 
 
+def sweep_grain_law(w, plan, out):
+    """Sec. 6.5 on the sweep: the in-plane standard deviation of sigma_xx
+    (root of the Eq. 20 mean square over the interior half of the layers,
+    averaged over the realisations of each grain size) against the grain
+    size, for the height-dependent density of the workload and for the same
+    grain maps with a height-independent density; log-log slopes."""
+    import numpy as np
+    import torch
+    from paper_1804_01830_amd import binding as Bd
+    from paper_1804_01830_amd import workloads as W
+    grains = (4, 8, 16, 32)
+    per = w["rho"].shape[0] // len(grains)
+    nz = w["n"][2]
+    lo, hi = nz // 4, nz - nz // 4
+
+    def s_xx(rho_np):
+        rho = torch.from_numpy(rho_np).to("cuda", dtype=torch.float32).contiguous()
+        plan.set_density(rho)
+        plan.stress(out)
+        ms = Bd.plane_mean_square(out)[:, 0, lo:hi].mean(dim=1).sqrt().cpu().numpy()
+        return [float(ms[g * per:(g + 1) * per].mean()) for g in range(len(grains))]
+
+    hd = s_xx(w["rho"])
+    flat = W.poly_sweep(*w["n"], z_decay=1e30)
+    hom = s_xx(flat["rho"])
+    slope = lambda v: float(np.polyfit(np.log(grains), np.log(v), 1)[0])
+    return {"grain_sizes": list(grains), "realisations_per_size": per,
+            "s_xx_height_dependent": [round(v, 5) for v in hd], "slope_height_dependent": round(slope(hd), 3),
+            "s_xx_height_independent": [round(v, 5) for v in hom], "slope_height_independent": round(slope(hom), 3)}
+
+
 def device_density(w, nb, dt):
     """The first nb densities on the device: the workload's channels, or for
     per-cell line fields the axis-basis channels built by the library
@@ -463,6 +494,8 @@ def main():
             hw, hper, hbytes = time_host_io(plan, rho, min(steps, 50), min(args.warmup, 5))
             host = dict(wall=hw, per=hper, bytes=hbytes, steps=min(steps, 50))
         stats_ms = None
+        if prec == 32 and args.workload == "sweep-64":
+            grain_law = sweep_grain_law(w, plan, out)
         if prec == 32:
             # Eq. (20) plane statistics of the stress just computed (one read of sigma)
             stream = torch.cuda.current_stream()
@@ -477,6 +510,7 @@ def main():
         info = plan.info()
         res[prec] = dict(plan=plan, info=info, wall=wall, per=per, passes=passes, calls=calls, steps=steps,
                          stats_ms=stats_ms, nye_ms=nye_ms,
+                         grain_law=grain_law if (prec == 32 and args.workload == "sweep-64") else None,
                          plan_s=plan_s, graph=graph, host=host, tune=Tn.to_dict(tune) if tune is not None else None,
                          out=out[0].double().cpu().numpy() if (B == 1 or plain_one) else None,
                          cells=Bp * nx * ny * nz)
@@ -547,6 +581,8 @@ def main():
         "roofline": roofline,
         "plan_info": plan_info,
     }
+    if r32.get("grain_law") is not None:
+        line["grain_law"] = r32["grain_law"]
     if r32["nye_ms"] is not None:
         line["axis_basis_channels"] = {
             "what": "rho[3l+g] = n t_l b_g from per-cell line fields (ddstress_nye_density), outside the step",
