@@ -263,6 +263,18 @@ ddstress_status ddstress_plan_destroy(ddstress_plan plan);
 ddstress_status ddstress_kernel_realspace(const ddstress_desc* desc, int32_t line, double* out,
                                           void* stream);
 
+/* Plane statistics with every stress call: with stats != NULL, each
+ * ddstress_stress / ddstress_stress_batch call also writes, for the
+ * realisations it evaluates, stats[b][v][k] = (1 / (Nx Ny)) sum_{i,j}
+ * sigma[b][v][k][j][i]^2 (Eq. 20; as ddstress_plane_mean_square, summed in
+ * another fixed order), computed in the inverse x pass from the values it
+ * writes (no second read of sigma): one FP64 sum of squares per row, then
+ * the rows of each plane in order. stats: device buffer of batch * 6 * Nz
+ * doubles, kept by the caller while set. The first non-NULL call allocates
+ * batch * 6 * Nz * Ny doubles of row sums for the plan's lifetime; NULL
+ * switches the statistics off. Drops the plan's captured graphs. */
+ddstress_status ddstress_plan_set_plane_stats(ddstress_plan plan, double* stats);
+
 /* Density channels in the axis basis (the Nye tensor) for line directions
  * that vary from cell to cell. Sec. 2.1 takes the stress of a volume element
  * as linear in the line direction t; that is exact for infinitesimal

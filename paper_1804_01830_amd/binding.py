@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STAT
 EXPORTS = ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
            "ddstress_set_density", "ddstress_stress",
            "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times",
-           "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_nye_density", "ddstress_plane_mean_square",
+           "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_plan_set_plane_stats", "ddstress_nye_density",
+           "ddstress_plane_mean_square",
            "ddstress_relax_create", "ddstress_relax_set_load", "ddstress_relax_iterate", "ddstress_relax_update_norm",
            "ddstress_relax_stress", "ddstress_relax_displacement", "ddstress_relax_get_info", "ddstress_relax_destroy",
            "ddstress_last_error", "ddstress_version")
@@ -96,6 +97,8 @@ def load(path=LIB_PATH):
     lib.ddstress_plan_share.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
     lib.ddstress_stress_batch.argtypes = [P, P, P, ctypes.c_int32, P]
     lib.ddstress_plan_get_pass_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.ddstress_plan_set_plane_stats.argtypes = [P, P]
+    lib.ddstress_plan_set_plane_stats.restype = ctypes.c_int
     lib.ddstress_nye_density.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                          ctypes.c_int32, P, P]
     lib.ddstress_nye_density.restype = ctypes.c_int
@@ -245,6 +248,20 @@ class Plan:
                 or tuple(t.shape) != (*lead, nz, ny, nx)):
             raise ValueError(f"expected a contiguous {where} {dt} tensor of shape {(*lead, nz, ny, nx)}, "
                              f"got {tuple(t.shape)} {t.dtype} on {t.device}")
+
+    def set_plane_stats(self, stats):
+        """With a CUDA float64 tensor (batch, 6, Nz), every stress call also
+        writes the Eq. (20) plane mean squares of its output there (computed in
+        the inverse x pass); None switches it off."""
+        import torch
+        if stats is not None:
+            nz = self.n[2]
+            if not stats.is_cuda or stats.dtype != torch.float64 or not stats.is_contiguous() \
+                    or tuple(stats.shape) != (self.batch, 6, nz):
+                raise ValueError(f"expected a contiguous CUDA float64 tensor of shape {(self.batch, 6, nz)}")
+        self._stats_ref = stats
+        check(load().ddstress_plan_set_plane_stats(self._h, ctypes.c_void_p(stats.data_ptr() if stats is not None
+                                                                            else None)))
 
     def set_profiling(self, enable=True):
         check(load().ddstress_plan_set_profiling(self._h, 1 if enable else 0))

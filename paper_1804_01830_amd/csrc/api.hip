@@ -161,6 +161,8 @@ struct ddstress_plan_s {
     int ex = 16, ey = 16, ez = 8;  // element classes of the x, y and fused z passes
     bool yx = false;               // inverse y and x as one kernel
     bool xy = false;               // forward x and y as one kernel
+    double* plane_stats = nullptr; // Eq. 20 output of every stress call (device), or none
+    DevBuf rowsq;                  // per-row sums of squares behind it
     double re_max = 0.0, im_max = 0.0;
     // per-pass event timing: events are pooled and reused between folds
     bool profiling = false;
@@ -398,9 +400,13 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     gi.ips = (int64_t)Py * s.wx;
     gi.ors = s.wx;
     gi.ops = (int64_t)Ny * s.wx;
+    // plane statistics (Eq. 20) from per-row sums of the inverse x pass
+    double* rowsq = p->plane_stats ? p->rowsq.as<double>() : nullptr;
+    const double inv_plane = 1.0 / ((double)Nx * (double)Ny);
     if constexpr (sizeof(T) == 4) {
         if (p->yx) {        // one kernel; the x pass's time shows as zero
-            launch_yx_inv(w1, sigma, B6 * Nz, Py, s.M, Ny, Nx, s.wx, tw, st);
+            launch_yx_inv(w1, sigma, B6 * Nz, Py, s.M, Ny, Nx, s.wx, tw, st, rowsq);
+            if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, p->plane_stats, st);
             p->mark(st);
             p->mark(st);
             return;
@@ -409,7 +415,8 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     launch_col_fft<T>(Py, p->ey, false, w1, w2, gi, tw, p->tk_y, st);
     p->mark(st);
     // x inverse: rows (b, v, z, y) -> Nx reals
-    launch_x_c2r<T>(s.M, p->ex, w2, sigma, B6 * Nz * Ny, Nx, s.wx, Nx, tw, p->rows_x, st);
+    launch_x_c2r<T>(s.M, p->ex, w2, sigma, B6 * Nz * Ny, Nx, s.wx, Nx, tw, p->rows_x, st, rowsq);
+    if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, p->plane_stats, st);
     p->mark(st);
 }
 
@@ -902,6 +909,17 @@ ddstress_status ddstress_plan_destroy(ddstress_plan plan) {
         if (!plan) return;
         (void)hipDeviceSynchronize();
         delete plan;
+    });
+}
+
+ddstress_status ddstress_plan_set_plane_stats(ddstress_plan plan, double* stats) {
+    return guarded([&] {
+        if (!plan) fail(DDSTRESS_E_INVALID, "plan is NULL");
+        if (stats && !plan->rowsq.p)
+            plan->rowsq.alloc((size_t)plan->shape.B * 6 * plan->shape.N[2] * (size_t)plan->shape.N[1] * sizeof(double),
+                              "plane statistics row sums");
+        if (stats != plan->plane_stats) plan->drop_graphs();      // captured launches carry the pointers
+        plan->plane_stats = stats;
     });
 }
 

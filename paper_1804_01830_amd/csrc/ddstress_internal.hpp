@@ -103,9 +103,38 @@ template <typename T>
 void launch_x_r2c(int M, int ev, const T* in, cplx<T>* out, int64_t nrows, int n_in, int64_t in_stride,
                   int64_t out_stride, const cplx<T>* tw, int rows_per_block, hipStream_t s);
 // Complex-to-real transform of length P = 2M along rows, keeping n_out reals.
+// With rowsq, also the sum of squares of each row's outputs (FP64) at
+// rowsq[row] (the plane statistics of Eq. 20, summed per plane afterwards).
 template <typename T>
 void launch_x_c2r(int M, int ev, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
-                  int64_t out_stride, const cplx<T>* tw, int rows_per_block, hipStream_t s);
+                  int64_t out_stride, const cplx<T>* tw, int rows_per_block, hipStream_t s,
+                  double* rowsq = nullptr);
+
+// Sum of squares of one row held by TC consecutive lanes of a wave (lane j
+// owns pairs j + TC m, m < E; n_out reals are valid), in FP64, reduced in a
+// fixed order; lane 0 writes it.
+template <typename T, int E, int TC>
+__device__ __forceinline__ void row_square_sum(const cplx<T>* reg, int j, int n_out, double* dst) {
+    static_assert(TC >= 1 && (TC & (TC - 1)) == 0, "power-of-two lanes per row");
+    if constexpr (TC > 64) {
+        // rows of more than 64 lanes (half lengths above 512) are never planned
+        if (j == 0) *dst = __builtin_nan("");
+        return;
+    }
+    double sq = 0.0;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int i0 = 2 * (j + TC * m);
+        if (i0 < n_out) sq += (double)reg[m].x * (double)reg[m].x;
+        if (i0 + 1 < n_out) sq += (double)reg[m].y * (double)reg[m].y;
+    }
+#pragma unroll
+    for (int o = TC / 2; o > 0; o >>= 1) sq += __shfl_xor(sq, o, TC);
+    if (j == 0) *dst = sq;
+}
+// Plane statistics from row sums: out[p] = inv * sum_{y < ny} rowsq[p ny + y]
+// (in order), for planes p < nplanes (stats.hip).
+void launch_rowsq_finish(const double* rowsq, int64_t nplanes, int ny, double inv, double* out, hipStream_t s);
 // Complex transform of length N along a strided axis, on tiles of consecutive columns.
 struct ColGeom {
     int ncols;             // valid columns (consecutive in memory)
@@ -167,7 +196,7 @@ void z_dispatch(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, c
 // block's LDS (yx_fused.hip): FP32, Py = 256, M = 128.
 bool yx_inv_fits(int Py, int M, int ny, int elem_bytes);
 void launch_yx_inv(const cplx<float>* in, float* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
-                   const cplx<float>* tw, hipStream_t s);
+                   const cplx<float>* tw, hipStream_t s, double* rowsq = nullptr);
 void launch_xy_fwd(const float* in, cplx<float>* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
                    const cplx<float>* tw, hipStream_t s);
 

@@ -94,7 +94,8 @@ template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T* __restrict__ out,
                                                int64_t nrows, int n_out, int64_t in_stride,
                                                int64_t out_stride, const cplx<T>* __restrict__ tw,
-                                               int rows_per_block, int pairs, int ld, int lsh) {
+                                               int rows_per_block, int pairs, int ld, int lsh,
+                                               double* __restrict__ rowsq) {
     constexpr int Tc = M / E;
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -140,6 +141,7 @@ __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T
             if (i0 + 1 < n_out) dst[i0 + 1] = reg[m].y;
         }
     }
+    if (rowsq) row_square_sum<T, E, Tc>(reg, j, n_out, rowsq + row);
 }
 
 // ----------------------------------------------------------------------------
@@ -411,7 +413,7 @@ static void x_r2c_ev(int M, const T* in, cplx<T>* out, int64_t nrows, int n_in, 
 
 template <typename T, int EV>
 static void x_c2r_ev(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
-                     int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
+                     int64_t out_stride, const cplx<T>* tw, int rows, double* rowsq, hipStream_t s) {
     const int64_t blocks = (nrows + rows - 1) / rows;
     const int pairs = pairs_ok(out, out_stride, n_out);
     switch (M) {
@@ -421,7 +423,7 @@ static void x_c2r_ev(int M, const cplx<T>* in, T* out, int64_t nrows, int n_out,
         const XLayout xl = x_lds_layout(L, E, (int)sizeof(T));                                            \
         const size_t lds = (size_t)rows * xl.ld * sizeof(cplx<T>);                                         \
         hipLaunchKernelGGL((k_x_c2r<T, L, E>), dim3((unsigned)blocks), dim3(rows * (L / E)), lds, s, in, out, \
-                           nrows, n_out, in_stride, out_stride, tw, rows, pairs, xl.ld, xl.s);                          \
+                           nrows, n_out, in_stride, out_stride, tw, rows, pairs, xl.ld, xl.s, rowsq);                   \
         break;                                                                                             \
     }
         DDS_FOR_LENGTHS(X_CASE, EV)
@@ -460,10 +462,10 @@ void launch_x_r2c(int M, int ev, const T* in, cplx<T>* out, int64_t nrows, int n
 
 template <typename T>
 void launch_x_c2r(int M, int ev, const cplx<T>* in, T* out, int64_t nrows, int n_out, int64_t in_stride,
-                  int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s) {
+                  int64_t out_stride, const cplx<T>* tw, int rows, hipStream_t s, double* rowsq) {
     if (nrows <= 0) return;
-    if (ev == 8) x_c2r_ev<T, 8>(M, in, out, nrows, n_out, in_stride, out_stride, tw, rows, s);
-    else if (ev == 16) x_c2r_ev<T, 16>(M, in, out, nrows, n_out, in_stride, out_stride, tw, rows, s);
+    if (ev == 8) x_c2r_ev<T, 8>(M, in, out, nrows, n_out, in_stride, out_stride, tw, rows, rowsq, s);
+    else if (ev == 16) x_c2r_ev<T, 16>(M, in, out, nrows, n_out, in_stride, out_stride, tw, rows, rowsq, s);
     else fail(DDSTRESS_E_INVALID, "x element class must be 8 or 16");
     check_hip(hipGetLastError(), "x c2r launch");
 }
@@ -518,7 +520,7 @@ void launch_z_fused(int N, int ev, int groups, const cplx<T>* in, cplx<T>* out, 
     template void launch_x_r2c<T>(int, int, const T*, cplx<T>*, int64_t, int, int64_t, int64_t, const cplx<T>*, \
                                   int, hipStream_t);                                                       \
     template void launch_x_c2r<T>(int, int, const cplx<T>*, T*, int64_t, int, int64_t, int64_t, const cplx<T>*, \
-                                  int, hipStream_t);                                                       \
+                                  int, hipStream_t, double*);                                              \
     template void launch_col_fft<T>(int, int, bool, const cplx<T>*, cplx<T>*, const ColGeom&, const cplx<T>*, \
                                     int, hipStream_t);                                                     \
     template void launch_z_fused<T>(int, int, int, const cplx<T>*, cplx<T>*, const T*, const ZGeom&,          \

@@ -1,8 +1,10 @@
 // In-plane mean square of each stress component at each height (Sec. 6,
-// Eq. 20): one block per (realisation, component, layer) plane, FP64
+// Eq. 20). Standalone: one block per (realisation, component, layer) plane, FP64
 // accumulation in a fixed order (four independent partial sums per thread,
 // then a tree over the block), so the result does not depend on anything
-// but the input. Reads the stress once: an HBM-bound reduction.
+// but the input. Reads the stress once: an HBM-bound reduction. Fused with
+// the stress call: the inverse x pass leaves one sum of squares per row and
+// k_rowsq_finish adds the rows of each plane in order.
 #include "ddstress_internal.hpp"
 
 namespace dds {
@@ -39,7 +41,25 @@ __global__ void __launch_bounds__(kStatThreads)
     if (t == 0) out[blockIdx.x] = red[0] * inv_plane;
 }
 
+__global__ void __launch_bounds__(256) k_rowsq_finish(const double* __restrict__ rowsq, int64_t nplanes, int ny,
+                                                      double inv, double* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nplanes) return;
+    const double* r = rowsq + p * ny;
+    double s = 0.0;
+    for (int y = 0; y < ny; ++y) s += r[y];
+    out[p] = s * inv;
+}
+
 }  // namespace
+
+void launch_rowsq_finish(const double* rowsq, int64_t nplanes, int ny, double inv, double* out, hipStream_t s) {
+    if (nplanes <= 0) return;
+    hipLaunchKernelGGL(k_rowsq_finish, dim3((unsigned)((nplanes + 255) / 256)), dim3(256), 0, s, rowsq, nplanes, ny,
+                       inv, out);
+    check_hip(hipGetLastError(), "plane statistics finish launch");
+}
+
 }  // namespace dds
 
 using namespace dds;

@@ -59,7 +59,7 @@ template <int PY, int M>
 __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __restrict__ in, float* __restrict__ out,
                                                        int64_t nplanes, int ny, int nx, int64_t wx,
                                                        const cplx<float>* __restrict__ tw, int xld, int xsh,
-                                                       int pairs) {
+                                                       int pairs, double* __restrict__ rowsq) {
     using T = float;
     constexpr int M1 = M + 1;
     constexpr int PLD = PY / 2;                          // plane column stride: rows y < Py/2
@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
                     if (i0 + 1 < nx) dst[i0 + 1] = reg[m].y;
                 }
             }
+            if (rowsq) row_square_sum<T, EX, TCX>(reg, jx, nx, rowsq + plane * (int64_t)ny + y);
         }
         __syncthreads();                             // the x exchanges are done before the next plane's columns
     }
@@ -291,7 +292,7 @@ void launch_xy_fwd(const float* in, cplx<float>* out, int64_t nplanes, int Py, i
 }
 
 void launch_yx_inv(const cplx<float>* in, float* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
-                   const cplx<float>* tw, hipStream_t s) {
+                   const cplx<float>* tw, hipStream_t s, double* rowsq) {
     if (nplanes <= 0) return;
     if (!yx_inv_fits(Py, M, ny, 4)) fail(DDSTRESS_E_INVALID, "plane does not fit the fused inverse y-x kernel");
     if (nplanes > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
@@ -300,7 +301,7 @@ void launch_yx_inv(const cplx<float>* in, float* out, int64_t nplanes, int Py, i
     // one resident block per CU walks over the planes
     const int64_t grid = nplanes < kYXBlocks ? nplanes : kYXBlocks;
     hipLaunchKernelGGL((k_yx_inv<256, 128>), dim3((unsigned)grid), dim3(kYXThreads), kYXLds, s, in, out, nplanes, ny,
-                       nx, wx, tw, xl.ld, xl.s, pairs);
+                       nx, wx, tw, xl.ld, xl.s, pairs, rowsq);
     check_hip(hipGetLastError(), "fused inverse y-x launch");
 }
 

@@ -79,3 +79,55 @@ def test_flat_grains_standard_deviation_does_not_depend_on_grain_size():
     slope = _slope(ds, ss)
     _say(f"[grain law] flat: s_xx {ss} slope {slope:.3f}")
     assert abs(slope) < 0.3
+
+
+@pytest.mark.parametrize("case", ["fp32-fused-planes", "fp32-passes", "fp64", "fp32-periodic"])
+def test_plane_statistics_fused_into_the_stress_call(case):
+    """Eq. (20) from the inverse x pass's epilogue against the standalone
+    reduction of the written stress: equal up to summation order (1e-13),
+    for the first nb realisations of a call, across graph replays."""
+    import torch
+    from paper_1804_01830_amd import binding as B
+    shape, prec, periodic = {"fp32-fused-planes": ((100, 70, 2), 32, (False, False)),
+                             "fp32-passes": ((20, 12, 5), 32, (False, False)),
+                             "fp64": ((20, 12, 5), 64, (False, False)),
+                             "fp32-periodic": ((32, 16, 4), 32, (True, True))}[case]
+    w = W.random_field(shape, n_lines=2, batch=3, seed=51, d=(1.0, 1.0, 2.0))
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=prec, batch=3, periodic=periodic,
+                       pbc_shells=2)
+    plan = B.Plan(desc)
+    if case == "fp32-fused-planes":
+        assert plan.info().yx_fused == 1
+    dt = torch.float32 if prec == 32 else torch.float64
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=dt).contiguous()
+    nx, ny, nz = shape
+    stats = torch.full((3, 6, nz), float("nan"), dtype=torch.float64, device="cuda")
+    plan.set_plane_stats(stats)
+    out = torch.empty((3, 6, nz, ny, nx), dtype=dt, device="cuda")
+    plan.stress_batch(rho, out, 3)
+    ref = B.plane_mean_square(out)
+    torch.cuda.synchronize()
+    err = ((stats - ref).abs().max() / ref.abs().max()).item()
+    _say(f"[fused stats] {case}: max rel diff to the standalone reduction {err:.2e}")
+    assert err < 1e-13
+    first = stats.clone()
+    # two realisations only: their planes are rewritten, the third keeps its values
+    stats.fill_(float("nan"))
+    plan.stress_batch(rho[:2], out[:2], 2)
+    torch.cuda.synchronize()
+    assert torch.equal(stats[:2], first[:2]) and torch.isnan(stats[2]).all()
+    # graph replays give the same bits
+    plan.set_graph(True)
+    for rep in range(3):
+        stats.fill_(float("nan"))
+        plan.stress_batch(rho, out, 3)
+        torch.cuda.synchronize()
+        assert torch.equal(stats, first), f"replay {rep}"
+        assert torch.isfinite(torch.randn(1 << 16, device="cuda").sum())
+    plan.set_graph(False)
+    plan.set_plane_stats(None)
+    stats.fill_(-1.0)
+    plan.stress_batch(rho, out, 3)
+    torch.cuda.synchronize()
+    assert (stats == -1.0).all()
+    plan.close()
