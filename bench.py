@@ -404,6 +404,20 @@ def relax_bench(args):
                                  "update_norm_last": res[p]["last"], "steps_to_1e-6": res[p]["conv"],
                                  "steps_run": res[p]["taken"]} for p in (32, 64)},
     }
+    from paper_1804_01830_amd import profiling as Pf
+    tr = Pf.stored_traffic(os.path.join(ROOT, "profiles"), line["config"]["workload"], 1, "k_relax_march",
+                           sources=Pf.RELAX_SOURCES)
+    if tr is not None:
+        line["roofline"]["traffic"] = int(tr)
+        line["roofline"]["traffic_vs_algorithmic"] = round(tr / b32, 3)
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calib_copy_bytes"] = 4 * n
     print(json.dumps(line), flush=True)
 
 
@@ -493,7 +507,7 @@ def main():
             graph = dict(wall=gw, per=gper)
             hw, hper, hbytes = time_host_io(plan, rho, min(steps, 50), min(args.warmup, 5))
             host = dict(wall=hw, per=hper, bytes=hbytes, steps=min(steps, 50))
-        stats_ms = None
+        stats_ms = fused_ms = None
         if prec == 32 and args.workload == "sweep-64":
             grain_law = sweep_grain_law(w, plan, out)
         if prec == 32:
@@ -507,9 +521,14 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             stats_ms = e0.elapsed_time(e1) / 20
+            # the same statistics fused into the stress call (inverse x epilogue)
+            plan.set_plane_stats(ms_out)
+            fw, fper, _, _ = time_path(plan, rho, out, min(steps, 100), min(args.warmup, 10), profile=False)
+            plan.set_plane_stats(None)
+            fused_ms = fw / min(steps, 100) * 1e3
         info = plan.info()
         res[prec] = dict(plan=plan, info=info, wall=wall, per=per, passes=passes, calls=calls, steps=steps,
-                         stats_ms=stats_ms, nye_ms=nye_ms,
+                         stats_ms=stats_ms, fused_ms=fused_ms, nye_ms=nye_ms,
                          grain_law=grain_law if (prec == 32 and args.workload == "sweep-64") else None,
                          plan_s=plan_s, graph=graph, host=host, tune=Tn.to_dict(tune) if tune is not None else None,
                          out=out[0].double().cpu().numpy() if (B == 1 or plain_one) else None,
@@ -577,7 +596,9 @@ def main():
         "plan_build_s": {"fp32": round(r32["plan_s"], 3), "fp64": round(r64["plan_s"], 3)},
         "plane_stats": {"what": "Eq. 20 mean square per plane of the FP32 stress (ddstress_plane_mean_square)",
                         "ms": round(r32["stats_ms"], 5),
-                        "gbs": round(B * 6 * nx * ny * nz * 4 / (r32["stats_ms"] * 1e-3) / 1e9, 1)},
+                        "gbs": round(B * 6 * nx * ny * nz * 4 / (r32["stats_ms"] * 1e-3) / 1e9, 1),
+                        "fused_ms_per_step": round(r32["fused_ms"], 5),
+                        "fused_note": "stress call with the statistics in the inverse x pass (ddstress_plan_set_plane_stats)"},
         "roofline": roofline,
         "plan_info": plan_info,
     }

@@ -18,6 +18,8 @@ Usage::
     python -m paper_1804_01830_amd.profiling trace <dir> <title> <command> > report.md
     python -m paper_1804_01830_amd.profiling traffic <fetch_dir> <write_dir> <bench_json_line_file> \\
         <copy_mib> <title> <command> > report.md
+    python -m paper_1804_01830_amd.profiling relax-traffic <fetch_dir> <write_dir> <bench_json_line_file> \\
+        <copy_mib> <title> <command> > report.md
 """
 import csv
 import glob
@@ -31,12 +33,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEVICE_SOURCES = ("csrc/passes.hip", "csrc/zfused.hpp", "csrc/z_serial_f32.hip", "csrc/z_serial_f64.hip",
                   "csrc/z_grouped_f32.hip", "csrc/z_grouped_f64.hip", "csrc/fft_device.hpp",
                   "csrc/ddstress_internal.hpp")
+RELAX_SOURCES = ("csrc/relax.hip", "csrc/fft_device.hpp", "csrc/ddstress_internal.hpp")
 
 
-def source_digest():
-    """sha256 over the device sources of the five passes."""
+def source_digest(sources=DEVICE_SOURCES):
+    """sha256 over device sources (default: those of the five passes)."""
     h = hashlib.sha256()
-    for rel in DEVICE_SOURCES:
+    for rel in sources:
         with open(os.path.join(HERE, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -133,11 +136,59 @@ def traffic_report(fetch_dir, write_dir, line_file, copy_mib, title, command):
     return "\n".join(out) + "\n"
 
 
-def stored_traffic(profiles_dir, workload, batch, kernel):
+def kernel_traffic(fetch_dir, write_dir, name_regex, copy_mib):
+    """Median FETCH_SIZE and WRITE_SIZE bytes per launch of the kernels whose
+    name matches `name_regex`, scaled by the plain copy of `copy_mib` MiB."""
+    result = {}
+    for counter, directory in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _csv(directory, "counter_collection.csv") if r["Counter_Name"] == counter]
+        k = [float(r["Counter_Value"]) for r in rows if re.search(name_regex, r["Kernel_Name"])]
+        other = [float(r["Counter_Value"]) for r in rows if "dds::" not in r["Kernel_Name"]]
+        if not k or not other:
+            raise SystemExit(f"{counter}: no launches matching {name_regex!r} or no copy kernel")
+        copy_kib = max(other)
+        factor = copy_mib * 1024.0 / copy_kib
+        kib = sorted(k)[len(k) // 2]
+        result[counter] = dict(launches=len(k), median_kib=kib, copy_kib=copy_kib, factor=factor,
+                               bytes=kib * 1024.0 * factor)
+    return result
+
+
+def relax_traffic_report(fetch_dir, write_dir, line_file, copy_mib, title, command):
+    """Traffic report of the FP32 relaxation step (`bench.py --relax`)."""
+    line = None
+    with open(line_file) as f:
+        for text in f:
+            text = text.strip()
+            if text.startswith("{") and '"metric"' in text:
+                line = json.loads(text)
+    if line is None:
+        raise SystemExit(f"no bench JSON line in {line_file}")
+    t = kernel_traffic(fetch_dir, write_dir, r"k_relax_march<float", copy_mib)
+    alg = line["roofline"]["algorithmic_bytes_per_launch"]
+    total = t["FETCH_SIZE"]["bytes"] + t["WRITE_SIZE"]["bytes"]
+    out = [f"# {title}", "", "Commands (from the repository root, one MI355X; one counter per run):", "", "```",
+           command.replace("{COUNTER}", "FETCH_SIZE"), command.replace("{COUNTER}", "WRITE_SIZE"), "```", "",
+           "Kernel: `k_relax_march<float, ...>` (one explicit step of the FP32 relaxation).", "",
+           "| counter | launches | median KiB per launch | copy kernel KiB | scale | bytes per launch |",
+           "|---|---:|---:|---:|---:|---:|"]
+    for k in ("FETCH_SIZE", "WRITE_SIZE"):
+        r = t[k]
+        out.append(f"| {k} | {r['launches']} | {r['median_kib']:.1f} | {r['copy_kib']:.1f} | "
+                   f"{r['factor']:.3f} | {r['bytes']:.4g} |")
+    out += ["", f"Scale: {copy_mib} MiB plain device copy (reads and writes {copy_mib} MiB).",
+            f"Algorithmic bytes per step (u and f read, u written, the ghost layers): {alg:.4g}; measured HBM "
+            f"traffic of the step kernel {total:.4g} ({total / alg:.3f} x algorithmic).", "",
+            "```", f"source_sha256: {source_digest(RELAX_SOURCES)}", f"workload: {line['config']['workload']}",
+            "batch: 1", "kernel: k_relax_march", f"traffic_bytes_per_launch: {total:.6g}", "```"]
+    return "\n".join(out) + "\n"
+
+
+def stored_traffic(profiles_dir, workload, batch, kernel, sources=DEVICE_SOURCES):
     """HBM bytes per launch from a traffic report in `profiles_dir` for this
     workload, batch and kernel, or None when there is none or the device
     sources have changed since it was taken."""
-    digest = source_digest()
+    digest = source_digest(sources)
     for path in sorted(glob.glob(os.path.join(profiles_dir, "*.md"))):
         with open(path) as f:
             text = f.read()
@@ -154,6 +205,8 @@ def main(argv):
         sys.stdout.write(trace_report(argv[1], argv[2], argv[3]))
     elif len(argv) >= 7 and argv[0] == "traffic":
         sys.stdout.write(traffic_report(argv[1], argv[2], argv[3], int(argv[4]), argv[5], argv[6]))
+    elif len(argv) >= 7 and argv[0] == "relax-traffic":
+        sys.stdout.write(relax_traffic_report(argv[1], argv[2], argv[3], int(argv[4]), argv[5], argv[6]))
     else:
         sys.stderr.write(__doc__)
         return 2

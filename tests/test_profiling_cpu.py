@@ -58,3 +58,25 @@ def test_stored_traffic_requires_current_sources(tmp_path):
     assert P.stored_traffic(str(prof), "disk-mixed-128x128x32", 1, "k_z_serial") is None
     (prof / "z.md").write_text(report.replace(P.source_digest(), "0" * 64))
     assert P.stored_traffic(str(prof), "disk-mixed-128x128x32", 8, "k_z_serial") is None
+
+
+def test_relax_traffic_report_selects_the_fp32_step_and_tracks_its_sources(tmp_path):
+    k32 = "void dds::(anonymous namespace)::k_relax_march<float, 64, 16>(float const*, float*)"
+    k64 = "void dds::(anonymous namespace)::k_relax_march<double, 64, 16>(double const*, double*)"
+    _write(tmp_path / "f", "FETCH_SIZE", [(k32, 1024, 1 << 20, 100.0), (k32, 1024, 1 << 20, 110.0),
+                                          (k32, 1024, 1 << 20, 105.0), (k64, 1024, 1 << 20, 9e9),
+                                          ("elementwise_kernel", 256, 1 << 20, 262144.0)])
+    _write(tmp_path / "w", "WRITE_SIZE", [(k32, 1024, 1 << 20, 50.0), (k64, 1024, 1 << 20, 9e9),
+                                          ("elementwise_kernel", 256, 1 << 20, 524288.0)])
+    line = {"metric": "m", "config": {"workload": "relax-layer"},
+            "roofline": {"algorithmic_bytes_per_launch": 300000}}
+    (tmp_path / "bench.json").write_text(json.dumps(line) + "\n")
+    report = P.relax_traffic_report(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "bench.json"), 512,
+                                     "t", "rocprofv3 --pmc {COUNTER} -- python3 bench.py --relax")
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "relax.md").write_text(report)
+    got = P.stored_traffic(str(prof), "relax-layer", 1, "k_relax_march", sources=P.RELAX_SOURCES)
+    assert got == 105.0 * 1024 * 2.0 + 50.0 * 1024
+    # the digest of the passes' sources does not stand in for the relaxation's
+    assert P.stored_traffic(str(prof), "relax-layer", 1, "k_relax_march") is None
