@@ -11,8 +11,9 @@
 // analogues), the total stress by Hooke's law with central differences.
 //
 // Kernels, all HBM-bound stencils: k_relax_load (f, surface terms, u = 0),
-// k_relax_step (one explicit step into the other state buffer, or the max of
-// |update| / dt), k_relax_ghost (both ghost layers), k_relax_stress.
+// k_relax_march (one explicit step into the other state buffer, marching
+// along z with LDS planes), k_relax_ghost (both ghost layers), k_relax_norm
+// (max |update| / dt), k_relax_stress.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -95,35 +96,26 @@ __device__ __forceinline__ void navier_update(const T* __restrict__ u, const T* 
     }
 }
 
-// MODE 0: un = u + dt v on the node layers. MODE 1: max |v| into *red (the
-// bit pattern of a non-negative double orders like the value).
-template <typename T, int MODE>
+// max |v| over the nodes into *red (the bit pattern of a non-negative double
+// orders like the value). One thread per node; the update norm only.
+template <typename T>
 __global__ void __launch_bounds__(kRelaxBX* kRelaxBY)
-    k_relax_step(const T* __restrict__ u, T* __restrict__ un, const T* __restrict__ f, RelaxGeom<T> g,
-                 unsigned long long* __restrict__ red) {
+    k_relax_norm(const T* __restrict__ u, const T* __restrict__ f, RelaxGeom<T> g, unsigned long long* __restrict__ red) {
     const int i = blockIdx.x * kRelaxBX + threadIdx.x;
     const int j = blockIdx.y * kRelaxBY + threadIdx.y;
     const int k = blockIdx.z;
     const bool ok = i < g.nx && j < g.ny;
     T v[3] = {T(0), T(0), T(0)}, u0[3];
     if (ok) navier_update(u, f, g, i, j, k, v, u0);
-    if constexpr (MODE == 0) {
-        if (ok) {
-            const int64_t o = (int64_t)(k + 1) * g.plane + (int64_t)j * g.nx + i;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) un[c * g.cstride + o] = u0[c] + g.dt * v[c];
-        }
-    } else {
-        __shared__ double sm[kRelaxBX * kRelaxBY];
-        const int t = threadIdx.y * kRelaxBX + threadIdx.x;
-        sm[t] = fmax(fmax(fabs((double)v[0]), fabs((double)v[1])), fabs((double)v[2]));
+    __shared__ double sm[kRelaxBX * kRelaxBY];
+    const int t = threadIdx.y * kRelaxBX + threadIdx.x;
+    sm[t] = fmax(fmax(fabs((double)v[0]), fabs((double)v[1])), fabs((double)v[2]));
+    __syncthreads();
+    for (int w = kRelaxBX * kRelaxBY / 2; w > 0; w >>= 1) {
+        if (t < w) sm[t] = fmax(sm[t], sm[t + w]);
         __syncthreads();
-        for (int w = kRelaxBX * kRelaxBY / 2; w > 0; w >>= 1) {
-            if (t < w) sm[t] = fmax(sm[t], sm[t + w]);
-            __syncthreads();
-        }
-        if (t == 0) atomicMax(red, (unsigned long long)__double_as_longlong(sm[0]));
     }
+    if (t == 0) atomicMax(red, (unsigned long long)__double_as_longlong(sm[0]));
 }
 
 // Ghost values at column (i, j) of the bottom (top = 0) or top surface from
@@ -400,7 +392,6 @@ struct ddstress_relax_s {
     DevBuf u[2], f, phi, red;
     int cur = 0;
     bool loaded = false;
-    bool march = true;      // z-marching step kernel (false: one thread per node, no LDS)
     int64_t steps = 0;
 
     int64_t nodes() const { return (int64_t)desc.n[0] * desc.n[1] * desc.n[2]; }
@@ -435,13 +426,8 @@ struct ddstress_relax_s {
         for (int s = 0; s < n; ++s) {
             T* a = u[cur].as<T>();
             T* b = u[cur ^ 1].as<T>();
-            if (march) {
-                hipLaunchKernelGGL((k_relax_march<T, TX, TY>), dim3(blocks), dim3(TX * TY), 0, st, a, b, f.as<T>(), g,
-                                   tiles_x, nchunks, kc);
-            } else {
-                hipLaunchKernelGGL((k_relax_step<T, 0>), grid(desc.n[2]), dim3(kRelaxBX, kRelaxBY), 0, st, a, b,
-                                   f.as<T>(), g, nullptr);
-            }
+            hipLaunchKernelGGL((k_relax_march<T, TX, TY>), dim3(blocks), dim3(TX * TY), 0, st, a, b, f.as<T>(), g,
+                               tiles_x, nchunks, kc);
             check_hip(hipGetLastError(), "relaxation step launch");
             hipLaunchKernelGGL((k_relax_ghost<T>), grid(2), dim3(kRelaxBX, kRelaxBY), 0, st, b, phi.as<T>(), g);
             check_hip(hipGetLastError(), "relaxation ghost launch");
@@ -451,8 +437,8 @@ struct ddstress_relax_s {
     template <typename T>
     void norm(hipStream_t st) {
         const RelaxGeom<T> g = make_geom<T>(desc, dt, A, B);
-        hipLaunchKernelGGL((k_relax_step<T, 1>), grid(desc.n[2]), dim3(kRelaxBX, kRelaxBY), 0, st, u[cur].as<T>(),
-                           nullptr, f.as<T>(), g, red.as<unsigned long long>());
+        hipLaunchKernelGGL((k_relax_norm<T>), grid(desc.n[2]), dim3(kRelaxBX, kRelaxBY), 0, st, u[cur].as<T>(),
+                           f.as<T>(), g, red.as<unsigned long long>());
         check_hip(hipGetLastError(), "relaxation norm launch");
     }
     template <typename T>
