@@ -197,3 +197,42 @@ def test_periodic_batches_graphs_and_shared_plans_are_bit_consistent():
         assert torch.equal(one[0], ref[r])
     shared.close()
     plan.close()
+
+
+def test_periodic_mirror_compression_matches_the_full_spectrum():
+    """The y mirror of a periodic plan (kept rows ky <= Py/2 with signs) gives
+    the stress of the full spectrum to rounding."""
+    from paper_1804_01830_amd import binding as B
+    w = W.random_field((16, 32, 3), n_lines=2, seed=45, d=(1.0, 1.0, 2.0))
+    got = {}
+    for flags in (0, B.FLAG_FULL_SPECTRUM):
+        import torch
+        desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=64, flags=flags,
+                           periodic=(True, True), pbc_shells=3)
+        plan = B.Plan(desc)
+        info = plan.info()
+        got[flags] = (info.mirror_y, info.mirror_z)
+        plan.set_density(torch.from_numpy(w["rho"]).cuda())
+        got[(flags, "s")] = plan.stress(plan.new_output()).cpu().numpy()
+        plan.close()
+    assert got[0][0] == 1 and got[B.FLAG_FULL_SPECTRUM] == (0, 0)
+    a, b = got[(0, "s")], got[(B.FLAG_FULL_SPECTRUM, "s")]
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
+@functools.lru_cache(maxsize=None)
+def _largest_plane():
+    w = W.random_field((512, 512, 2), n_lines=1, seed=46, d=(1.0, 1.0, 1.0))
+    ref = stress_fft_reference_periodic(w["rho"][0], w["d"], w["lines"], w["mu"], w["nu"], periodic=(True, True),
+                                        shells=1)
+    return w, ref
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_periodic_largest_plane(precision):
+    """512 x 512 periodic plane (the longest periodic axes), one shell."""
+    w, ref = _largest_plane()
+    got = gpu_stress(w, precision, periodic=(True, True), pbc_shells=1)[0]
+    comp, whole = rel_l2(got, ref)
+    _say(f"[pbc 512x512] precision={precision} per component {np.array2string(comp, precision=2)} whole {whole:.2e}")
+    assert np.all(comp <= TOL[precision]) and whole <= TOL[precision]
