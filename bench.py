@@ -12,7 +12,7 @@ per-cell random in-plane angle, b = (cos phi, sin phi, 1)/sqrt 2), cells
 dx = dy = 1, dz = 2, radial Gaussian density with 10 % noise; FP32 transforms
 with an FP64 kernel precompute, compared with the plain FP64 path.
 
-Prints one JSON line. ``--gpus`` above 1 is rejected: this build runs on one GPU.
+Prints one JSON line. ``--gpus`` above 1 is rejected: the benchmark runs on one GPU.
 """
 import argparse
 import json
@@ -449,7 +449,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the stress evaluation of one grid (or one batch of grids) "
-              "is not sharded across GPUs in this build; use --gpus 1", file=sys.stderr)
+              "is not sharded across GPUs; use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.serve:
         serve_bench(args)
