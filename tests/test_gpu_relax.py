@@ -139,3 +139,18 @@ def test_layer_256_full_size_steps(precision):
     err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
     _say(f"[relax 256] precision={precision} rel L2 u {err:.2e}")
     assert err <= (1e-12 if precision == 64 else 1e-5)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_relaxed_total_stress_is_traction_free_on_both_surfaces(precision):
+    """Eq. (16b) on the device: after any number of steps the total sigma_zz,
+    sigma_yz, sigma_xz vanish on the first and last node layers (the ghost
+    layers carry the discretised condition), while inside they do not."""
+    w = W.random_stress((40, 24, 7), seed=12, d=(1.0, 1.0, 2.0), smooth=True)
+    _, tot, _, _ = _device(w, precision, 37)
+    scale = np.abs(w["sigma"]).max()
+    tol = 1e-12 if precision == 64 else 2e-5
+    for v in (2, 3, 4):
+        for k in (0, 6):
+            assert np.abs(tot[v, k]).max() <= tol * scale, (v, k)
+    assert np.abs(tot[2, 3]).max() > 1e-3 * scale

@@ -1,7 +1,8 @@
 """Stress server on the GPU: requests of several shapes arrive while others
 run, are batched per shape into slots that share their shape's kernel
 spectrum, and overlap on several streams. Each served result must equal the
-same density evaluated alone (plan with batch 1, direct launches) bit for bit.
+same density evaluated alone (plan with batch 1, direct launches) bit for bit,
+open and periodic shapes alike.
 """
 import numpy as np
 import pytest
@@ -14,7 +15,14 @@ pytestmark = pytest.mark.gpu
 
 def _key(w, precision=32):
     return ShapeKey(n=tuple(w["n"]), d=tuple(w["d"]), mu=w["mu"], nu=w["nu"],
-                    lines=tuple(tuple(map(float, t)) for t in w["lines"]), precision=precision)
+                    lines=tuple(tuple(map(float, t)) for t in w["lines"]), precision=precision,
+                    periodic=w.get("periodic", (False, False)), pbc_shells=w.get("pbc_shells", 0))
+
+
+def _periodic(w, shells):
+    w = dict(w)
+    w["periodic"], w["pbc_shells"] = (True, True), shells
+    return w
 
 
 @pytest.mark.parametrize("precision", [32, 64])
@@ -24,7 +32,8 @@ def test_served_results_equal_alone(precision):
     dt = torch.float32 if precision == 32 else torch.float64
     pools = [W.random_field((24, 16, 8), n_lines=2, batch=4, seed=1, d=(1.0, 1.0, 2.0)),
              W.random_field((40, 20, 6), n_lines=1, batch=4, seed=2),
-             W.random_field((16, 16, 16), n_lines=2, batch=4, seed=3, d=(2.0, 1.0, 1.0))]
+             W.random_field((16, 16, 16), n_lines=2, batch=4, seed=3, d=(2.0, 1.0, 1.0)),
+             _periodic(W.random_field((32, 16, 4), n_lines=2, batch=4, seed=4, d=(1.0, 1.0, 2.0)), 3)]
     keys = [_key(w, precision) for w in pools]
     dens = [torch.from_numpy(w["rho"]).to("cuda", dtype=dt) for w in pools]
     rng = np.random.default_rng(9)
@@ -32,7 +41,7 @@ def test_served_results_equal_alone(precision):
     ex = GpuExecutor(use_graph=True)
     reqs = []
     for i, t in enumerate(arrivals):
-        s = int(rng.integers(3))
+        s = int(rng.integers(len(pools)))
         j = int(rng.integers(4))
         reqs.append(Request(i, keys[s], rho=dens[s][j], arrival=float(t) + ex.clock()))
         reqs[-1].src = (s, j)
@@ -43,7 +52,8 @@ def test_served_results_equal_alone(precision):
     assert st["requests"] == len(reqs) and st["mean_batch"] >= 1.0
     alone = {}
     for s, w in enumerate(pools):
-        desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision, batch=4)
+        desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision, batch=4,
+                           periodic=w.get("periodic", (False, False)), pbc_shells=w.get("pbc_shells", 0))
         plan = B.Plan(desc)
         for j in range(4):
             out = torch.empty((1, 6, *dens[s].shape[2:]), dtype=dt, device="cuda")
