@@ -360,6 +360,15 @@ ddstress_status ddstress_relax_iterate(ddstress_relax r, int32_t n_steps, void* 
  * the size of the next step's update divided by dt. Synchronises `stream`. */
 ddstress_status ddstress_relax_update_norm(ddstress_relax r, double* out, void* stream);
 
+/* Iterate until the update norm falls to rel_tol times its value at the
+ * first check of this call, or until max_steps steps have been taken, checking
+ * every check_every steps (>= 1). A stopping rule of the caller's choosing
+ * (the paper gives none): steps_taken and final_norm (either may be NULL)
+ * report the outcome; reaching max_steps is not an error. Synchronises
+ * `stream` at every check. */
+ddstress_status ddstress_relax_solve(ddstress_relax r, double rel_tol, int32_t max_steps, int32_t check_every,
+                                     int32_t* steps_taken, double* final_norm, void* stream);
+
 /* sigma_total = sigma_dis + sigma(u) on the nodes (sigma_total may be
  * sigma_dis itself). Enqueued on `stream`. */
 ddstress_status ddstress_relax_stress(ddstress_relax r, const void* sigma_dis, void* sigma_total, void* stream);

@@ -23,7 +23,7 @@ EXPORTS = ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create
            "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_plan_set_plane_stats", "ddstress_nye_density",
            "ddstress_plane_mean_square",
            "ddstress_relax_create", "ddstress_relax_set_load", "ddstress_relax_iterate", "ddstress_relax_update_norm",
-           "ddstress_relax_stress", "ddstress_relax_displacement", "ddstress_relax_get_info", "ddstress_relax_destroy",
+           "ddstress_relax_solve", "ddstress_relax_stress", "ddstress_relax_displacement", "ddstress_relax_get_info", "ddstress_relax_destroy",
            "ddstress_last_error", "ddstress_version")
 PASS_NAMES = ("x_r2c", "y_fwd", "z_fused", "y_inv", "x_c2r")
 
@@ -108,6 +108,8 @@ def load(path=LIB_PATH):
     lib.ddstress_relax_set_load.argtypes = [P, P, P]
     lib.ddstress_relax_iterate.argtypes = [P, ctypes.c_int32, P]
     lib.ddstress_relax_update_norm.argtypes = [P, ctypes.POINTER(ctypes.c_double), P]
+    lib.ddstress_relax_solve.argtypes = [P, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), P]
     lib.ddstress_relax_stress.argtypes = [P, P, P, P]
     lib.ddstress_relax_displacement.argtypes = [P, P, P]
     lib.ddstress_relax_get_info.argtypes = [P, ctypes.POINTER(RelaxInfo)]
@@ -329,6 +331,15 @@ class Relax:
         out = ctypes.c_double()
         check(load().ddstress_relax_update_norm(self._h, ctypes.byref(out), _stream_handle(stream)))
         return out.value
+
+    def solve(self, rel_tol, max_steps, check_every=500, stream=None):
+        """Iterate until the update norm falls to rel_tol of its first value
+        (or max_steps); returns (steps taken, final update norm)."""
+        steps = ctypes.c_int32()
+        norm = ctypes.c_double()
+        check(load().ddstress_relax_solve(self._h, float(rel_tol), int(max_steps), int(check_every),
+                                          ctypes.byref(steps), ctypes.byref(norm), _stream_handle(stream)))
+        return steps.value, norm.value
 
     def stress(self, sigma_dis, out=None, stream=None):
         import torch

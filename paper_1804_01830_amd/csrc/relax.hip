@@ -367,6 +367,11 @@ RelaxGeom<T> make_geom(const ddstress_relax_desc& d, double dt, double A, double
     return g;
 }
 
+// Re-raise the status of a nested entry point (its message is already set).
+void check_status(ddstress_status s) {
+    if (s != DDSTRESS_OK) throw Error{s, ddstress_last_error()};
+}
+
 void validate_relax(const ddstress_relax_desc* d) {
     if (!d) fail(DDSTRESS_E_INVALID, "descriptor is NULL");
     if (d->n[0] < 1 || d->n[1] < 1) fail(DDSTRESS_E_INVALID, "Nx and Ny must be >= 1");
@@ -513,6 +518,31 @@ ddstress_status ddstress_relax_update_norm(ddstress_relax r, double* out, void* 
         check_hip(hipMemcpyAsync(&bits, r->red.p, sizeof bits, hipMemcpyDeviceToHost, st), "norm readback");
         check_hip(hipStreamSynchronize(st), "norm");
         std::memcpy(out, &bits, sizeof(double));
+    });
+}
+
+ddstress_status ddstress_relax_solve(ddstress_relax r, double rel_tol, int32_t max_steps, int32_t check_every,
+                                     int32_t* steps_taken, double* final_norm, void* stream) {
+    return guarded([&] {
+        if (!r) fail(DDSTRESS_E_INVALID, "plan is NULL");
+        if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) fail(DDSTRESS_E_INVALID, "rel_tol must be finite and >= 0");
+        if (max_steps < 0 || check_every < 1) fail(DDSTRESS_E_INVALID, "max_steps >= 0 and check_every >= 1");
+        if (!r->loaded) fail(DDSTRESS_E_STATE, "solve before set_load");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        double first = 0.0, now = 0.0;
+        check_status(ddstress_relax_update_norm(r, &first, stream));
+        now = first;
+        int32_t taken = 0;
+        while (taken < max_steps && now > rel_tol * first) {
+            const int32_t n = std::min(check_every, max_steps - taken);
+            if (r->desc.precision == 32) r->iterate<float>(n, st);
+            else r->iterate<double>(n, st);
+            r->steps += n;
+            taken += n;
+            check_status(ddstress_relax_update_norm(r, &now, stream));
+        }
+        if (steps_taken) *steps_taken = taken;
+        if (final_norm) *final_norm = now;
     });
 }
 

@@ -122,3 +122,10 @@ def test_plane_statistics_arguments_are_validated_before_any_device_work():
     for args in ((None, 32, n, 1, dummy), (dummy, 32, n, 1, None), (dummy, 16, n, 1, dummy),
                  (dummy, 32, n, 0, dummy), (dummy, 64, bad_n, 1, dummy)):
         assert lib.ddstress_plane_mean_square(*args, None) == B.E_INVALID
+
+
+def test_relaxation_solve_rejects_bad_arguments_without_a_plan():
+    lib = B.load()
+    import ctypes
+    steps, norm = ctypes.c_int32(), ctypes.c_double()
+    assert lib.ddstress_relax_solve(None, 1e-6, 10, 1, ctypes.byref(steps), ctypes.byref(norm), None) == B.E_INVALID

@@ -85,12 +85,11 @@ def test_uniform_linear_load_relaxes_to_the_closed_form():
     r = B.Relax(n, d, mu, nu, precision=64)
     s = torch.from_numpy(np.ascontiguousarray(sig)).cuda()
     r.set_load(s)
-    for _ in range(40):
-        r.iterate(200)
-        if r.update_norm() < 1e-12:
-            break
+    first = r.update_norm()
+    steps, final = r.solve(1e-13, 20000, check_every=200)
+    assert steps < 20000 and final <= 1e-13 * first              # stopped by the tolerance
+    assert steps == r.info().steps and steps % 200 == 0
     tot = r.stress(s).cpu().numpy()
-    steps = r.info().steps
     r.close()
     k = nu / (1 - nu)
     _say(f"[relax closed form] steps {steps}")
