@@ -7,6 +7,30 @@
 
 namespace dds {
 
+// Logical block -> (kx tile, ky), P (even) rows of nt tiles: row 0, then for
+// q = 1 .. P/2 - 1 the tiles of rows q and P - q interleaved (tile t of row q,
+// tile t of row P - q, tile t + 1 of row q, ...), then row P/2. Rows ky and
+// P - ky read the same stored spectrum tile when the y mirror applies; as
+// neighbouring blocks (on one XCD, by xcd_block) the second read finds it in
+// L2 instead of HBM. A bijection onto [0, nt) x [0, P).
+__device__ __forceinline__ void z_block_coords(int blk, int nt, int P, int& tile, int& ky) {
+    if (blk < nt || P < 4) {            // row 0 (P = 2: rows 0 and 1, no pairs)
+        tile = blk % nt;
+        ky = blk / nt;
+        return;
+    }
+    const int b = blk - nt;
+    const int paired = (P / 2 - 1) * 2 * nt;
+    if (b < paired) {
+        const int q = b / (2 * nt) + 1, w = b % (2 * nt);
+        tile = w >> 1;
+        ky = (w & 1) ? P - q : q;
+    } else {
+        tile = b - paired;
+        ky = P / 2;
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Fused z pass, single-group form. A block owns `tk` consecutive kx columns at
 // one ky and one group of Tc * tk threads. For every realisation b it
@@ -44,8 +68,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
     const int c = threadIdx.x % tk;
     const int j = threadIdx.x / tk;
     const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int tile = blk % g.ntiles;
-    const int ky = blk / g.ntiles;
+    int tile, ky;
+    z_block_coords(blk, g.ntiles, g.nky, tile, ky);
     const int col = tile * tk + c;
     const bool valid = col < g.ncols;
     const int colc = valid ? col : 0;
@@ -241,8 +265,8 @@ __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ i
     const int c = t % tk;
     const int j = t / tk;
     const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int tile = blk % g.ntiles;
-    const int ky = blk / g.ntiles;
+    int tile, ky;
+    z_block_coords(blk, g.ntiles, g.nky, tile, ky);
     const int col = tile * tk + c;
     const bool valid = col < g.ncols;
     const int colc = valid ? col : 0;
