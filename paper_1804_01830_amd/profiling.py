@@ -20,6 +20,7 @@ Usage::
         <copy_mib> <title> <command> > report.md
     python -m paper_1804_01830_amd.profiling relax-traffic <fetch_dir> <write_dir> <bench_json_line_file> \\
         <copy_mib> <title> <command> > report.md
+    python -m paper_1804_01830_amd.profiling kernels <fetch_dir> <write_dir> <copy_mib> <title> <command> > report.md
 """
 import csv
 import glob
@@ -184,6 +185,35 @@ def relax_traffic_report(fetch_dir, write_dir, line_file, copy_mib, title, comma
     return "\n".join(out) + "\n"
 
 
+def kernels_report(fetch_dir, write_dir, copy_mib, title, command, min_launches=4):
+    """Median FETCH_SIZE and WRITE_SIZE bytes per launch of every library
+    kernel shape (name, block, grid) with at least `min_launches` launches,
+    scaled by the plain copy of `copy_mib` MiB."""
+    def load(directory, counter):
+        out = {}
+        for r in _csv(directory, "counter_collection.csv"):
+            if r["Counter_Name"] == counter:
+                out.setdefault((short_name(r["Kernel_Name"]), int(r["Workgroup_Size"]), int(r["Grid_Size"])),
+                               []).append(float(r["Counter_Value"]))
+        return out
+    f, w = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy_f = max(v for k, vs in f.items() if "dds::" not in k[0] for v in vs)
+    copy_w = max(v for k, vs in w.items() if "dds::" not in k[0] for v in vs)
+    sf, sw = copy_mib * 1024.0 / copy_f, copy_mib * 1024.0 / copy_w
+    med = lambda vs: sorted(vs)[len(vs) // 2]
+    out = [f"# {title}", "", "Commands (from the repository root, one MI355X; one counter per run):", "", "```",
+           command.replace("{COUNTER}", "FETCH_SIZE"), command.replace("{COUNTER}", "WRITE_SIZE"), "```", "",
+           f"Median HBM bytes per launch: counter KiB x 1024 x scale, the scale from a {copy_mib} MiB plain device "
+           f"copy (FETCH_SIZE x {sf:.3f}, WRITE_SIZE x {sw:.3f}).", "",
+           "| kernel | block | grid | launches | fetch MB | write MB |", "|---|---:|---:|---:|---:|---:|"]
+    for k in sorted(f, key=lambda k: -med(f[k])):
+        if "dds::" not in k[0] or len(f[k]) < min_launches:
+            continue
+        out.append(f"| `{k[0]}` | {k[1]} | {k[2]} | {len(f[k])} | {med(f[k]) * 1024 * sf / 1e6:.1f} | "
+                   f"{med(w.get(k, [0.0])) * 1024 * sw / 1e6:.1f} |")
+    return "\n".join(out) + "\n"
+
+
 def stored_traffic(profiles_dir, workload, batch, kernel, sources=DEVICE_SOURCES):
     """HBM bytes per launch from a traffic report in `profiles_dir` for this
     workload, batch and kernel, or None when there is none or the device
@@ -205,6 +235,8 @@ def main(argv):
         sys.stdout.write(trace_report(argv[1], argv[2], argv[3]))
     elif len(argv) >= 7 and argv[0] == "traffic":
         sys.stdout.write(traffic_report(argv[1], argv[2], argv[3], int(argv[4]), argv[5], argv[6]))
+    elif len(argv) >= 6 and argv[0] == "kernels":
+        sys.stdout.write(kernels_report(argv[1], argv[2], int(argv[3]), argv[4], argv[5]))
     elif len(argv) >= 7 and argv[0] == "relax-traffic":
         sys.stdout.write(relax_traffic_report(argv[1], argv[2], argv[3], int(argv[4]), argv[5], argv[6]))
     else:

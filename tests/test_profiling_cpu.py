@@ -80,3 +80,16 @@ def test_relax_traffic_report_selects_the_fp32_step_and_tracks_its_sources(tmp_p
     assert got == 105.0 * 1024 * 2.0 + 50.0 * 1024
     # the digest of the passes' sources does not stand in for the relaxation's
     assert P.stored_traffic(str(prof), "relax-layer", 1, "k_relax_march") is None
+
+
+def test_kernels_report_scales_every_library_kernel(tmp_path):
+    ka = "void dds::k_yx_inv<256, 128>(float const*)"
+    kb = "void dds::k_xy_fwd<256, 128>(float const*)"
+    _write(tmp_path / "f", "FETCH_SIZE", [(ka, 1024, 4096, 10.0)] * 5 + [(kb, 1024, 4096, 3.0)] * 5 +
+           [("elementwise_kernel", 256, 1 << 20, 262144.0)])
+    _write(tmp_path / "w", "WRITE_SIZE", [(ka, 1024, 4096, 7.0)] * 5 + [(kb, 1024, 4096, 2.0)] * 5 +
+           [("elementwise_kernel", 256, 1 << 20, 524288.0)])
+    rep = P.kernels_report(str(tmp_path / "f"), str(tmp_path / "w"), 512, "t", "cmd {COUNTER}")
+    rows = [l for l in rep.splitlines() if l.startswith("| `")]
+    assert rows[0].startswith("| `dds::k_yx_inv") and rows[1].startswith("| `dds::k_xy_fwd")
+    assert f"| {10.0 * 1024 * 2.0 / 1e6:.1f} | {7.0 * 1024 / 1e6:.1f} |" in rows[0]
