@@ -22,9 +22,16 @@ template <typename T>
 __device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename T>
 __device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+// Fused multiply-add. Complex products are written with it explicitly, each
+// component one rounded product and one fused multiply-add, so their rounding
+// does not depend on which product the compiler would contract in a given
+// context: every kernel that forms the same product gets the same bits.
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    return {fmad(a.x, b.x, -(a.y * b.y)), fmad(a.x, b.y, a.y * b.x)};
 }
 template <typename T>
 __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
@@ -34,7 +41,7 @@ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
 template <bool FWD, typename T>
 __device__ __forceinline__ cplx<T> twmul(cplx<T> a, cplx<T> w) {
     if (FWD) return cmul(a, w);
-    return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
+    return {fmad(a.x, w.x, a.y * w.y), fmad(a.y, w.x, -(a.x * w.y))};
 }
 
 // Multiply by -i (forward) or +i (inverse).
@@ -205,7 +212,9 @@ struct RowPad {        // element i of row r at r*ld + i + (i >> s): one pad ele
 // One radix-R Stockham stage. Butterfly b = j + Tc*q (q < E/R) reads
 // x[b + r N/R], multiplies by exp(-/+ 2 pi i (b mod Ns) r / (Ns R)), applies
 // the length-R DFT and writes (b / Ns) Ns R + (b mod Ns) + r Ns.
-template <typename T, int N, int E, bool FWD, int Ns, int R, class Lay>
+// HZ: elements N/2 .. N-1 of the input are zero (zero padding); the first
+// stage then never reads them (same values).
+template <typename T, int N, int E, bool FWD, int Ns, int R, bool HZ, class Lay>
 __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
                                           const cplx<T>* __restrict__ tw, bool act) {
     constexpr int Tc = N / E;
@@ -234,7 +243,10 @@ __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay l
 #pragma unroll
             for (int r = 1; r < R; ++r) v[q][r] = twmul<FWD>(v[q][r], tw[k * r * (N / (Ns * R))]);
         }
-        dftR<R, FWD>(v[q]);
+        if constexpr (first && HZ)
+            dftR_hz<R, FWD>(v[q]);
+        else
+            dftR<R, FWD>(v[q]);
     }
     if constexpr (last) {
 #pragma unroll
@@ -255,13 +267,13 @@ __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay l
     }
 }
 
-template <typename T, int N, int E, bool FWD, int Ns, class Lay>
+template <typename T, int N, int E, bool FWD, int Ns, bool HZ, class Lay>
 __device__ __forceinline__ void fft_stages(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
                                            const cplx<T>* __restrict__ tw, bool act) {
     if constexpr (Ns < N) {
         constexpr int R = cmin(cmin(8, E), N / Ns);
-        fft_stage<T, N, E, FWD, Ns, R>(reg, lds, lay, c, j, tw, act);
-        fft_stages<T, N, E, FWD, Ns * R>(reg, lds, lay, c, j, tw, act);
+        fft_stage<T, N, E, FWD, Ns, R, HZ>(reg, lds, lay, c, j, tw, act);
+        fft_stages<T, N, E, FWD, Ns * R, HZ>(reg, lds, lay, c, j, tw, act);
     }
 }
 
@@ -299,10 +311,11 @@ __device__ __forceinline__ void load_tw_stages(cplx<T> (&w)[TWC], int j, const c
 // twiddles in registers (see load_tw_stages): one barrier before the reads and
 // one before the writes of each stage serve all K, whose exchanges use the LDS
 // regions lds + k * region. HZ: inputs m >= E/2 of every transform are zero
-// (zero-padded data) and are not read.
+// (zero-padded data) and are not read. Threads with act == false (whole
+// waves) take part in the barriers without touching LDS.
 template <typename T, int N, int E, bool FWD, bool HZ, int Ns, int R, int KT, int K, int TWC, class Lay>
 __device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
-                                           Lay lay, int c, int j) {
+                                           Lay lay, int c, int j, bool act) {
     constexpr int Tc = N / E;
     constexpr int NB = E / R;
     constexpr bool first = (Ns == 1);
@@ -317,12 +330,14 @@ __device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (
                 for (int r = 0; r < (HZ ? (R + 1) / 2 : R); ++r) v[k][q][r] = reg[k][q + r * NB];
     } else {
         __syncthreads();
+        if (act) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+            for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int q = 0; q < NB; ++q)
+                for (int q = 0; q < NB; ++q)
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[k][q][r] = lds[k * region + lay(j + Tc * q + r * (N / R), c)];
+                    for (int r = 0; r < R; ++r) v[k][q][r] = lds[k * region + lay(j + Tc * q + r * (N / R), c)];
+        }
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -344,45 +359,49 @@ __device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (
                 for (int r = 0; r < R; ++r) reg[k][q + r * NB] = v[k][q][r];
     } else {
         __syncthreads();
+        if (act) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+            for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                const int b = j + Tc * q;
-                const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
+                for (int q = 0; q < NB; ++q) {
+                    const int b = j + Tc * q;
+                    const int base = (b / Ns) * Ns * R + (b & (Ns - 1));
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[k * region + lay(base + r * Ns, c)] = v[k][q][r];
-            }
+                    for (int r = 0; r < R; ++r) lds[k * region + lay(base + r * Ns, c)] = v[k][q][r];
+                }
+        }
     }
 }
 
 template <typename T, int N, int E, bool FWD, bool HZ, int Ns, int KT, int K, int TWC, class Lay>
 __device__ __forceinline__ void fftk_stages(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
-                                            Lay lay, int c, int j) {
+                                            Lay lay, int c, int j, bool act) {
     if constexpr (Ns < N) {
         constexpr int R = cmin(cmin(8, E), N / Ns);
-        fftk_stage<T, N, E, FWD, HZ, Ns, R, KT, K, TWC>(reg, w, lds, region, lay, c, j);
+        fftk_stage<T, N, E, FWD, HZ, Ns, R, KT, K, TWC>(reg, w, lds, region, lay, c, j, act);
         fftk_stages<T, N, E, FWD, HZ, Ns * R, (Ns == 1 ? KT : KT + (E / R) * (R - 1)), K, TWC>(reg, w, lds, region,
-                                                                                              lay, c, j);
+                                                                                              lay, c, j, act);
     }
 }
 
 template <typename T, int N, int E, bool FWD, bool HZ, int K, int TWC, class Lay>
 __device__ __forceinline__ void fft_regs_k(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
-                                           Lay lay, int c, int j) {
+                                           Lay lay, int c, int j, bool act = true) {
     static_assert(N % E == 0, "E must divide N");
-    fftk_stages<T, N, E, FWD, HZ, 1, 0, K, TWC>(reg, w, lds, region, lay, c, j);
+    fftk_stages<T, N, E, FWD, HZ, 1, 0, K, TWC>(reg, w, lds, region, lay, c, j, act);
 }
 
 // Full transform of length N on the register distribution described above.
 // `tw` points at the table of exp(-2 pi i k / N), k < N. Every thread of the
 // block must call it (it contains barriers when N > E); threads with act ==
-// false (whole waves) take part in the barriers without touching LDS.
-template <typename T, int N, int E, bool FWD, class Lay>
+// false (whole waves) take part in the barriers without touching LDS. With
+// HZ the upper half of the input is zero padding and its registers are not read.
+template <typename T, int N, int E, bool FWD, bool HZ = false, class Lay>
 __device__ __forceinline__ void fft_regs(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
                                          const cplx<T>* __restrict__ tw, bool act = true) {
     static_assert(N % E == 0, "E must divide N");
-    fft_stages<T, N, E, FWD, 1>(reg, lds, lay, c, j, tw, act);
+    static_assert(!HZ || E >= 2, "a zero upper half needs two elements per thread");
+    fft_stages<T, N, E, FWD, 1, HZ>(reg, lds, lay, c, j, tw, act);
 }
 
 }  // namespace dds

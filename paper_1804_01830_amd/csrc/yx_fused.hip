@@ -24,16 +24,26 @@
 // arithmetic is that of the two plain passes at element classes 8 (y) and 16
 // (x), so results are identical.
 //
+// Twiddles. Vector-memory loads and stores complete in issue order, so a
+// twiddle load issued after a column prefetch (or after a round's stores)
+// would wait for it. The y twiddles are therefore loaded into registers once
+// per plane, before the prefetches, and the x phase reads its two tables
+// (exp(-2 pi i k / M) and exp(-2 pi i k / P), k < M) from the top 2M values of
+// LDS, which the row exchanges leave free.
+//
 // Forward. Every (realisation, channel, z) plane of the density holds Ny rows
-// of Nx reals. One block transforms each row along x (real-to-complex, the
-// split of k_x_r2c) and keeps the (M+1) x Ny spectrum plane in LDS, column c
+// of Nx reals. A block (one resident per CU, walking over planes, the next
+// plane's rows requested before the current plane's column transforms)
+// transforms each row along x (real-to-complex, the split of k_x_r2c; with an
+// open x axis the upper half of every packed row is zero and the first stage
+// skips it) and keeps the (M+1) x Ny spectrum plane in LDS, column c
 // at (M - c) (Py/2) + (y ^ (c & 15)) (reversed, so the columns consumed first
 // free a contiguous range at the end), then transforms the kx columns along y
 // (rows >= Ny are the zero padding; 8 elements per thread) in rounds of
 // 16-column groups whose exchange regions take the LDS freed so far (16, 32,
 // 32, 32 and 17 columns at Py = 256, M = 128), writing the Py rows of each
-// column. Same arithmetic as the separate passes at element classes 16 (x)
-// and 8 (y).
+// column. Same values as the separate passes at element classes 16 (x) and
+// 8 (y): the first stages skip only inputs that are zero.
 #include "ddstress_internal.hpp"
 
 namespace dds {
@@ -66,14 +76,15 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
     constexpr int GC = 16, EY = 8, TCY = PY / EY;        // y: 16 columns per group, Tc threads per column
     constexpr int GT = GC * TCY;                         // threads per group
     constexpr int EX = 16, TCX = M / EX;                 // x: Tc threads per row
+    constexpr int TWY = tw_count(PY, EY);                // y twiddles per thread
     static_assert(kYXThreads % GT == 0 && kYXThreads / TCX >= PY / 2, "launch shape");
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* const twl = lds + kYXLds / (int)sizeof(cplx<T>) - 2 * M;   // x-phase twiddles (see below)
     const int t = threadIdx.x;
     const int gi = t / GT, tl = t % GT, cl = tl % GC, jy0 = tl / GC;    // column-transform roles
     const int jx0 = t % TCX, y = t / TCX;                                // row-transform roles
     const bool row_ok = y < ny;
-    const cplx<T>* tw2 = tw + (2 * M - 1);
     int jy = jy0;
 
     // The block walks over planes; the loads of the next round (or of the next
@@ -97,7 +108,15 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
         int jx = jx0;
         jy = jy0;
         asm volatile("" : "+v"(jx), "+v"(jy));
-        // 1. inverse y of the kx columns, rounds of groups
+        // 1. inverse y of the kx columns, rounds of groups. The twiddles are
+        //    loaded once per plane, before the next round's columns are
+        //    requested: vector loads (and stores) complete in issue order, so
+        //    a twiddle load issued after them would wait for them.
+        cplx<T> twy[TWY];
+        load_tw_stages<T, PY, EY, 1, 0>(twy, jy, tw + (PY - 1));
+        // the x-phase tables, written to the top of LDS after the rounds (which
+        // use all of it): exp(-2 pi i k / M) and exp(-2 pi i k / P), k < M
+        const cplx<T> tv = t < 2 * M ? tw[t < M ? (M - 1) + t : (2 * M - 1) + (t - M)] : cplx<T>{T(0), T(0)};
         for (int c0 = 0; c0 < M1;) {
             int groups, ncols;
             yx_round<PY, M, GC, GT>(c0, groups, ncols);
@@ -105,26 +124,28 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
             const bool act = gi < groups;                // whole waves
             const int c = c0 + gi * GC + cl;
             const bool valid = act && c < M1;
-            cplx<T> reg[EY];
+            cplx<T> reg[1][EY];
 #pragma unroll
-            for (int m = 0; m < EY; ++m) reg[m] = nxt[m];
+            for (int m = 0; m < EY; ++m) reg[0][m] = nxt[m];
             if (c0 + ncols < M1) load_cols(plane, c0 + ncols);
             cplx<T>* scratch = lds + c0 * PLD + (act ? gi : 0) * (PY * GC);
-            fft_regs<T, PY, EY, false>(reg, scratch, ColMajor{GC}, cl, jy, tw + (PY - 1), act);
+            fft_regs_k<T, PY, EY, false, false, 1, TWY>(reg, twy, scratch, 0, ColMajor{GC}, cl, jy, act);
             __syncthreads();                             // the groups' last exchange reads are done
             if (valid) {
 #pragma unroll
                 for (int m = 0; m < (EY + 1) / 2; ++m) {    // rows y = j + Tc m < Py/2
                     const int yy = jy + TCY * m;
-                    if (yy < ny) lds[c * PLD + (yy ^ (c & 15))] = reg[m];
+                    if (yy < ny) lds[c * PLD + (yy ^ (c & 15))] = reg[0][m];
                 }
             }
             c0 += ncols;
         }
         if (plane + gridDim.x < nplanes) load_cols(plane + gridDim.x, 0);
+        if (t < 2 * M) twl[t] = tv;                  // the rounds' exchange reads are done
         __syncthreads();
 
-        // 2. per row: split into Z', inverse x, Nx reals
+        // 2. per row: split into Z', inverse x, Nx reals (twiddles from LDS: they
+        //    never wait behind the next plane's column loads)
         cplx<T> reg[EX];
 #pragma unroll
         for (int m = 0; m < EX; ++m) {
@@ -134,11 +155,11 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
             const cplx<T> xk = lds[k * PLD + (yr ^ (k & 15))];
             const cplx<T> xm = cconj(lds[km * PLD + (yr ^ (km & 15))]);
             const cplx<T> e = cadd(xk, xm);
-            const cplx<T> wd = twmul<false>(csub(xk, xm), tw2[k]);   // exp(+2 pi i k/P) (X[k] - conj X[M-k])
+            const cplx<T> wd = twmul<false>(csub(xk, xm), twl[M + k]);   // exp(+2 pi i k/P) (X[k] - conj X[M-k])
             reg[m] = {e.x - wd.y, e.y + wd.x};                       // e + i wd
         }
         __syncthreads();                             // the plane is read: its LDS serves the x exchanges
-        fft_regs<T, M, EX, false>(reg, lds, RowPad{xld, xsh}, y, jx, tw + (M - 1));
+        fft_regs<T, M, EX, false>(reg, lds, RowPad{xld, xsh}, y, jx, twl);
         if (row_ok) {
             T* dst = out + plane * (int64_t)ny * nx + (int64_t)y * nx;
             if (pairs) {
@@ -163,10 +184,11 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
 }
 
 
-template <int PY, int M>
+template <int PY, int M, bool HX>
 __global__ void __launch_bounds__(kYXThreads) k_xy_fwd(const float* __restrict__ in, cplx<float>* __restrict__ out,
-                                                       int ny, int nx, int64_t wx, const cplx<float>* __restrict__ tw,
-                                                       int xld, int xsh, int pairs) {
+                                                       int64_t nplanes, int ny, int nx, int64_t wx,
+                                                       const cplx<float>* __restrict__ tw, int xld, int xsh,
+                                                       int pairs) {
     using T = float;
     constexpr int M1 = M + 1;
     constexpr int PLD = PY / 2;
@@ -174,99 +196,136 @@ __global__ void __launch_bounds__(kYXThreads) k_xy_fwd(const float* __restrict__
     constexpr int GT = GC * TCY;
     constexpr int CAP = kYXLds / (int)sizeof(cplx<T>);
     constexpr int EX = 16, TCX = M / EX;
+    constexpr int EL = HX ? EX / 2 : EX;                 // row elements that can be non-zero
+    constexpr int TWY = tw_count(PY, EY);                // y twiddles per thread
     static_assert(kYXThreads % GT == 0 && kYXThreads / TCX >= PY / 2, "launch shape");
+    constexpr int CAPF = CAP - 2 * M;                    // the top 2M values hold the x-phase twiddles
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
     const int t = threadIdx.x;
-    const int64_t plane = blockIdx.x;
+    // x-phase twiddle tables in LDS (read there, they never wait behind the
+    // previous plane's stores): exp(-2 pi i k / M) and exp(-2 pi i k / P), k < M
+    cplx<T>* const twl = lds + CAPF;
+    for (int i = t; i < 2 * M; i += kYXThreads) twl[i] = i < M ? tw[(M - 1) + i] : tw[(2 * M - 1) + (i - M)];
 
-    // 1. per row: reals in pairs, length-M transform, split into M+1 outputs
-    {
-        const int j = t % TCX, y = t / TCX;
-        const bool row_ok = y < ny;
-        const T* src = in + plane * (int64_t)ny * nx + (int64_t)(row_ok ? y : 0) * nx;
-        cplx<T> reg[EX];
+    // The block walks over planes; the rows of the next plane are requested
+    // before the current plane's column transforms. Per-thread indices are
+    // re-derived at each use (here and per plane below): keeps addresses and
+    // twiddles from being held in registers across the loop.
+    cplx<T> nxt[EL];
+    // Past the last plane (have == false) the registers are set to zero, so the
+    // previous rows are dead once they are consumed.
+    auto load_rows = [&](int64_t pl, bool have) {
+        int tr = t;
+        asm volatile("" : "+v"(tr));
+        const int jx0 = tr % TCX, y = tr / TCX;
+        const bool row_ok = have && y < ny;
+        if (!have) pl = 0;
+        const T* src = in + pl * (int64_t)ny * nx + (int64_t)(row_ok ? y : 0) * nx;
         if (pairs) {
             const cplx<T>* src2 = reinterpret_cast<const cplx<T>*>(src);
 #pragma unroll
-            for (int m = 0; m < EX; ++m) {
-                const int q = j + TCX * m;
-                reg[m] = (row_ok && 2 * q < nx) ? src2[q] : cplx<T>{T(0), T(0)};
+            for (int m = 0; m < EL; ++m) {
+                const int q = jx0 + TCX * m;
+                nxt[m] = (row_ok && 2 * q < nx) ? src2[q] : cplx<T>{T(0), T(0)};
             }
         } else {
 #pragma unroll
-            for (int m = 0; m < EX; ++m) {
-                const int i0 = 2 * (j + TCX * m);
+            for (int m = 0; m < EL; ++m) {
+                const int i0 = 2 * (jx0 + TCX * m);
                 T a = T(0), b = T(0);
                 if (row_ok && i0 < nx) a = src[i0];
                 if (row_ok && i0 + 1 < nx) b = src[i0 + 1];
-                reg[m] = {a, b};
+                nxt[m] = {a, b};
             }
         }
+    };
+    int64_t plane = blockIdx.x;
+    load_rows(plane, plane < nplanes);
+    for (; plane < nplanes; plane += gridDim.x) {
+        int tt = t;
+        asm volatile("" : "+v"(tt));
+        const int j = tt % TCX, yr = tt / TCX;
+        // 1. per row: reals in pairs, length-M transform, split into M+1 outputs
+        cplx<T> reg[EX];
+#pragma unroll
+        for (int m = 0; m < EX; ++m) reg[m] = m < EL ? nxt[m] : cplx<T>{T(0), T(0)};
         const RowPad lay{xld, xsh};
-        fft_regs<T, M, EX, true>(reg, lds, lay, y, j, tw + (M - 1));
+        fft_regs<T, M, EX, true, HX>(reg, lds, lay, yr, j, twl);
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < EX; ++m) lds[lay(j + TCX * m, y)] = reg[m];
+        for (int m = 0; m < EX; ++m) lds[lay(j + TCX * m, yr)] = reg[m];
         __syncthreads();
-        const cplx<T>* tw2 = tw + (2 * M - 1);
-        const T half = T(0.5);
-        cplx<T> xs[EX];
-#pragma unroll
-        for (int m = 0; m < EX; ++m) {
-            const int k = j + TCX * m;
-            const cplx<T> zk = lds[lay(k, y)];
-            const cplx<T> zm = cconj(lds[lay((M - k) & (M - 1), y)]);
-            const cplx<T> e = cadd(zk, zm);
-            const cplx<T> wd = cmul(tw2[k], csub(zk, zm));          // W_P^k (Z[k] - conj Z[M-k])
-            xs[m] = {half * (e.x + wd.y), half * (e.y - wd.x)};     // e/2 - (i/2) wd
-        }
-        const cplx<T> z0 = lds[lay(0, y)];
-        __syncthreads();                                 // the row spectra are read: the plane takes their LDS
-        if (row_ok) {
+        {
+            const T half = T(0.5);
+            cplx<T> xs[EX];
 #pragma unroll
             for (int m = 0; m < EX; ++m) {
                 const int k = j + TCX * m;
-                lds[(M - k) * PLD + (y ^ (k & 15))] = xs[m];
+                const cplx<T> zk = lds[lay(k, yr)];
+                const cplx<T> zm = cconj(lds[lay((M - k) & (M - 1), yr)]);
+                const cplx<T> e = cadd(zk, zm);
+                const cplx<T> wd = cmul(twl[M + k], csub(zk, zm));      // W_P^k (Z[k] - conj Z[M-k])
+                xs[m] = {half * (e.x + wd.y), half * (e.y - wd.x)};     // e/2 - (i/2) wd
             }
-            if (j == 0) lds[0 * PLD + (y ^ (M & 15))] = cplx<T>{z0.x - z0.y, T(0)};     // column M
+            const cplx<T> z0 = lds[lay(0, yr)];
+            T zM = z0.x - z0.y;                          // column M
+            // The split is finished before the barrier: only its outputs are held across it.
+#pragma unroll
+            for (int m = 0; m < EX; ++m) asm volatile("" : "+v"(xs[m].x), "+v"(xs[m].y));
+            asm volatile("" : "+v"(zM));
+            __syncthreads();                             // the row spectra are read: the plane takes their LDS
+            if (yr < ny) {
+#pragma unroll
+                for (int m = 0; m < EX; ++m) {
+                    const int k = j + TCX * m;
+                    lds[(M - k) * PLD + (yr ^ (k & 15))] = xs[m];
+                }
+                if (j == 0) lds[0 * PLD + (yr ^ (M & 15))] = cplx<T>{zM, T(0)};
+            }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // 2. forward y of the kx columns, rounds of groups growing into the freed LDS
-    {
+        // 2. forward y of the kx columns (rows >= Ny are zero padding, Ny <= Py/2),
+        //    rounds of groups growing into the freed LDS. The twiddles are loaded
+        //    once per plane, before the next plane's rows are requested: vector
+        //    loads (and stores) complete in issue order, so a twiddle load issued
+        //    after the rows or a round's stores would wait for them.
         cplx<T>* dst = out + plane * (int64_t)PY * wx;
-        const int gi = t / GT, tl = t % GT, cl = tl % GC;
-        int j = tl / GC;
+        const int gi = tt / GT, cl = (tt % GT) % GC;
+        int jy = (tt % GT) / GC;
+        cplx<T> twy[TWY];
+        load_tw_stages<T, PY, EY, 1, 0>(twy, jy, tw + (PY - 1));
+        load_rows(plane + gridDim.x, plane + gridDim.x < nplanes);
         for (int c0 = 0; c0 < M1;) {
-            asm volatile("" : "+v"(j));   // per round: keeps the twiddles from being held across rounds
+            asm volatile("" : "+v"(jy));  // per round: keeps the twiddles from being held across rounds
             int groups = kYXThreads / GT, ncols = 0;
             for (; groups > 1; --groups) {
                 ncols = groups * GC < M1 - c0 ? groups * GC : M1 - c0;
                 const int g2 = (ncols + GC - 1) / GC;
-                if (g2 * PY * GC <= CAP - (M1 - c0 - ncols) * PLD) break;
+                if (g2 * PY * GC <= CAPF - (M1 - c0 - ncols) * PLD) break;
             }
             ncols = groups * GC < M1 - c0 ? groups * GC : M1 - c0;
             groups = (ncols + GC - 1) / GC;
             const bool act = gi < groups;
             const int c = c0 + gi * GC + cl;
             const bool valid = act && c < M1;
-            cplx<T> reg[EY];
+            cplx<T> col[1][EY];
 #pragma unroll
             for (int m = 0; m < EY; ++m) {
-                const int y = j + TCY * m;
-                reg[m] = (valid && 2 * m < EY && y < ny) ? lds[(M - c) * PLD + (y ^ (c & 15))]
-                                                         : cplx<T>{T(0), T(0)};
+                const int yy = jy + TCY * m;
+                col[0][m] = (valid && 2 * m < EY && yy < ny) ? lds[(M - c) * PLD + (yy ^ (c & 15))]
+                                                              : cplx<T>{T(0), T(0)};
             }
             cplx<T>* scratch = lds + (M1 - c0 - ncols) * PLD + (act ? gi : 0) * (PY * GC);
-            fft_regs<T, PY, EY, true>(reg, scratch, ColMajor{GC}, cl, j, tw + (PY - 1), act);
+            fft_regs_k<T, PY, EY, true, true, 1, TWY>(col, twy, scratch, 0, ColMajor{GC}, cl, jy, act);
             if (valid) {
 #pragma unroll
-                for (int m = 0; m < EY; ++m) dst[(int64_t)(j + TCY * m) * wx + c] = reg[m];
+                for (int m = 0; m < EY; ++m) dst[(int64_t)(jy + TCY * m) * wx + c] = col[0][m];
             }
             c0 += ncols;
         }
+        __syncthreads();                             // the last exchanges are read before the next plane's rows
     }
 }
 
@@ -283,11 +342,20 @@ void launch_xy_fwd(const float* in, cplx<float>* out, int64_t nplanes, int Py, i
                    const cplx<float>* tw, hipStream_t s) {
     if (nplanes <= 0) return;
     if (!yx_inv_fits(Py, M, ny, 4)) fail(DDSTRESS_E_INVALID, "plane does not fit the fused forward x-y kernel");
+    if ((size_t)(Py / 2) * x_lds_layout(M, 16, 4).ld + 2 * (size_t)M > (size_t)kYXLds / sizeof(cplx<float>))
+        fail(DDSTRESS_E_INVALID, "row exchanges and twiddle tables exceed the fused forward kernel's LDS");
     if (nplanes > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
     const XLayout xl = x_lds_layout(M, 16, 4);
     const int pairs = (reinterpret_cast<uintptr_t>(in) % 8 == 0 && nx % 2 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((k_xy_fwd<256, 128>), dim3((unsigned)nplanes), dim3(kYXThreads), kYXLds, s, in, out, ny, nx,
-                       wx, tw, xl.ld, xl.s, pairs);
+    // one resident block per CU walks over the planes; rows of nx <= M reals
+    // (an open x axis) leave the upper half of the packed row zero
+    const int64_t grid = nplanes < kYXBlocks ? nplanes : kYXBlocks;
+    if (nx <= M)
+        hipLaunchKernelGGL((k_xy_fwd<256, 128, true>), dim3((unsigned)grid), dim3(kYXThreads), kYXLds, s, in, out,
+                           nplanes, ny, nx, wx, tw, xl.ld, xl.s, pairs);
+    else
+        hipLaunchKernelGGL((k_xy_fwd<256, 128, false>), dim3((unsigned)grid), dim3(kYXThreads), kYXLds, s, in, out,
+                           nplanes, ny, nx, wx, tw, xl.ld, xl.s, pairs);
     check_hip(hipGetLastError(), "fused forward x-y launch");
 }
 
@@ -295,6 +363,8 @@ void launch_yx_inv(const cplx<float>* in, float* out, int64_t nplanes, int Py, i
                    const cplx<float>* tw, hipStream_t s, double* rowsq) {
     if (nplanes <= 0) return;
     if (!yx_inv_fits(Py, M, ny, 4)) fail(DDSTRESS_E_INVALID, "plane does not fit the fused inverse y-x kernel");
+    if ((size_t)(Py / 2) * x_lds_layout(M, 16, 4).ld + 2 * (size_t)M > (size_t)kYXLds / sizeof(cplx<float>))
+        fail(DDSTRESS_E_INVALID, "row exchanges and twiddle tables exceed the fused inverse kernel's LDS");
     if (nplanes > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
     const XLayout xl = x_lds_layout(M, 16, 4);
     const int pairs = (reinterpret_cast<uintptr_t>(out) % 8 == 0 && nx % 2 == 0) ? 1 : 0;

@@ -148,15 +148,22 @@ def test_tuning_outside_limits_is_rejected():
     assert e.value.status == B.E_INVALID
 
 
-@pytest.mark.parametrize("grid", [(128, 128, 4), (100, 77, 3), (65, 128, 2)])
-def test_fused_inverse_yx_gives_separate_bits(grid):
+@pytest.mark.parametrize("grid,periodic", [((128, 128, 4), (False, False)), ((100, 77, 3), (False, False)),
+                                           ((65, 128, 2), (False, False)),
+                                           # more planes than resident blocks (288 forward, 576
+                                           # inverse): blocks walk on to further planes
+                                           ((120, 100, 48), (False, False)),
+                                           # periodic x: full-length rows (no zero upper half)
+                                           ((256, 72, 48), (True, False))])
+def test_fused_inverse_yx_gives_separate_bits(grid, periodic):
     """The fused inverse y-x and forward x-y kernels (planes kept in LDS) give
     the bits of the separate passes at the same element classes (x 16, y 8),
     on full and ragged planes, with several realisations."""
     import torch
     from paper_1804_01830_amd import binding as B
     w = W.random_field(grid, n_lines=1, batch=2, seed=21, d=(1.0, 1.0, 2.0))
-    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=32, batch=2)
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=32, batch=2, periodic=periodic,
+                       pbc_shells=2)
     base = B.Plan(desc).info()
     outs = []
     for yx, xy in ((1, 1), (2, 1), (1, 2), (2, 2)):
