@@ -214,6 +214,31 @@ def kernels_report(fetch_dir, write_dir, copy_mib, title, command, min_launches=
     return "\n".join(out) + "\n"
 
 
+def counters_report(dirs, title, commands, notes=(), min_launches=4):
+    """Median value per launch of every counter collected in the rocprofv3
+    `--pmc` runs under `dirs`, for every library kernel shape (name, block,
+    grid) with at least `min_launches` launches."""
+    vals, names = {}, []
+    for directory in dirs:
+        for r in _csv(directory, "counter_collection.csv"):
+            if "dds::" not in r["Kernel_Name"]:
+                continue
+            key = (short_name(r["Kernel_Name"]), int(r["Workgroup_Size"]), int(r["Grid_Size"]))
+            c = r["Counter_Name"]
+            if c not in names:
+                names.append(c)
+            vals.setdefault(key, {}).setdefault(c, []).append(float(r["Counter_Value"]))
+    med = lambda vs: sorted(vs)[len(vs) // 2]
+    out = [f"# {title}", "", "Commands (from the repository root, one MI355X):", "", "```", *commands, "```", "",
+           *notes, "", "| kernel | block | grid | launches | " + " | ".join(names) + " |",
+           "|---|---:|---:|---:|" + "---:|" * len(names)]
+    rows = [(k, v) for k, v in vals.items() if len(next(iter(v.values()))) >= min_launches]
+    for k, v in sorted(rows, key=lambda kv: kv[0]):
+        cells = [f"{med(v[c]):.4g}" if c in v else "" for c in names]
+        out.append(f"| `{k[0]}` | {k[1]} | {k[2]} | {len(next(iter(v.values())))} | " + " | ".join(cells) + " |")
+    return "\n".join(out) + "\n"
+
+
 def stored_traffic(profiles_dir, workload, batch, kernel, sources=DEVICE_SOURCES):
     """HBM bytes per launch from a traffic report in `profiles_dir` for this
     workload, batch and kernel, or None when there is none or the device

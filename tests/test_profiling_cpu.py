@@ -93,3 +93,21 @@ def test_kernels_report_scales_every_library_kernel(tmp_path):
     rows = [l for l in rep.splitlines() if l.startswith("| `")]
     assert rows[0].startswith("| `dds::k_yx_inv") and rows[1].startswith("| `dds::k_xy_fwd")
     assert f"| {10.0 * 1024 * 2.0 / 1e6:.1f} | {7.0 * 1024 / 1e6:.1f} |" in rows[0]
+
+
+def test_counters_report_takes_medians_per_kernel_shape(tmp_path):
+    z = "void dds::k_z_serial<float, 64, 4, 3, 8>(dds::cplx<float> const*)"
+    y = "void dds::(anonymous namespace)::k_yx_inv<256, 128>(dds::cplx<float> const*)"
+    # two counter runs; the copy kernel and a shape launched too few times are left out
+    _write(tmp_path / "a", "VALUBusy", [(z, BLOCK, GRID, 40.0), (z, BLOCK, GRID, 44.0), (z, BLOCK, GRID, 42.0),
+                                        (z, BLOCK, GRID, 90.0), (z, 256, GRID, 5.0), (y, 1024, 262144, 30.0),
+                                        (y, 1024, 262144, 31.0), (y, 1024, 262144, 29.0), (y, 1024, 262144, 33.0),
+                                        ("elementwise_kernel", 256, 1 << 20, 1.0)])
+    _write(tmp_path / "b", "SQ_WAVES", [(z, BLOCK, GRID, 8704.0)] * 4 + [(y, 1024, 262144, 4096.0)] * 4)
+    rep = P.counters_report([str(tmp_path / "a"), str(tmp_path / "b")], "t", ["cmd a", "cmd b"], min_launches=4)
+    lines = [l for l in rep.splitlines() if l.startswith("| `")]
+    assert len(lines) == 2 and "| VALUBusy | SQ_WAVES |" in rep
+    zl = [l for l in lines if "k_z_serial" in l][0]
+    assert "| 128 |" in zl and "| 44 | 8704 |" in zl                  # median of 40, 42, 44, 90
+    yl = [l for l in lines if "k_yx_inv" in l][0]
+    assert "`dds::k_yx_inv<256, 128>`" in yl and "| 31 | 4096 |" in yl
