@@ -232,7 +232,10 @@ ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info);
 /* Per-pass timing with HIP events recorded on the stream of each stress()
  * call: enable != 0 switches it on (and clears the totals), 0 switches it off.
  * The five passes are, in order: x real-to-complex, y forward, fused z
- * (forward z + contraction + inverse z), y inverse, x complex-to-real. */
+ * (forward z + contraction + inverse z), y inverse, x complex-to-real. A pass
+ * that runs inside the previous one's kernel (y forward with x forward, x
+ * inverse with y inverse, where a plane fits one block's LDS) records no event
+ * of its own and reports zero. Every event record takes some stream time. */
 ddstress_status ddstress_plan_set_profiling(ddstress_plan plan, int32_t enable);
 
 /* Graph replay: with enable != 0, stress() and stress_batch() record their

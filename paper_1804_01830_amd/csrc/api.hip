@@ -164,9 +164,13 @@ struct ddstress_plan_s {
     double* plane_stats = nullptr; // Eq. 20 output of every stress call (device), or none
     DevBuf rowsq;                  // per-row sums of squares behind it
     double re_max = 0.0, im_max = 0.0;
-    // per-pass event timing: events are pooled and reused between folds
+    // per-pass event timing: events are pooled and reused between folds; each
+    // recorded call fills 6 slots with pool indices (a pass fused into the
+    // previous one repeats its slot instead of recording another event, since
+    // every event record takes stream time)
     bool profiling = false;
-    std::vector<hipEvent_t> events;    // 6 per recorded call
+    std::vector<hipEvent_t> events;
+    std::vector<size_t> slots;
     size_t ev_used = 0;
     double pass_ms[5] = {0, 0, 0, 0, 0};
     int64_t timed_calls = 0;
@@ -197,19 +201,26 @@ struct ddstress_plan_s {
             check_hip(hipEventCreate(&e), "event create");
             events.push_back(e);
         }
-        check_hip(hipEventRecord(events[ev_used++], st), "event record");
+        check_hip(hipEventRecord(events[ev_used], st), "event record");
+        slots.push_back(ev_used++);
+    }
+    void mark_fused() {     // the pass just enqueued ran inside the previous one: zero time
+        if (!profiling) return;
+        slots.push_back(slots.back());
     }
     void fold_events() {
-        for (size_t i = 0; i + 5 < ev_used; i += 6) {
-            check_hip(hipEventSynchronize(events[i + 5]), "event sync");
+        for (size_t i = 0; i + 5 < slots.size(); i += 6) {
+            check_hip(hipEventSynchronize(events[slots[i + 5]]), "event sync");
             for (int k = 0; k < 5; ++k) {
+                if (slots[i + k] == slots[i + k + 1]) continue;
                 float ms = 0.f;
-                check_hip(hipEventElapsedTime(&ms, events[i + k], events[i + k + 1]), "event time");
+                check_hip(hipEventElapsedTime(&ms, events[slots[i + k]], events[slots[i + k + 1]]), "event time");
                 pass_ms[k] += ms;
             }
             ++timed_calls;
         }
         ev_used = 0;
+        slots.clear();
     }
 };
 
@@ -348,7 +359,7 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
         if (p->xy) {        // one kernel; the y pass's time shows as zero
             launch_xy_fwd(rho, w2, BC * Nz, Py, s.M, Ny, Nx, s.wx, tw, st);
             p->mark(st);
-            p->mark(st);
+            p->mark_fused();
             fused_fwd = true;
         }
     }
@@ -408,7 +419,7 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
             launch_yx_inv(w1, sigma, B6 * Nz, Py, s.M, Ny, Nx, s.wx, tw, st, rowsq);
             if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, p->plane_stats, st);
             p->mark(st);
-            p->mark(st);
+            p->mark_fused();
             return;
         }
     }
@@ -881,6 +892,7 @@ ddstress_status ddstress_plan_set_profiling(ddstress_plan plan, int32_t enable) 
     return guarded([&] {
         if (!plan) fail(DDSTRESS_E_INVALID, "plan is NULL");
         plan->ev_used = 0;
+        plan->slots.clear();
         plan->profiling = enable != 0;
         for (double& v : plan->pass_ms) v = 0.0;
         plan->timed_calls = 0;

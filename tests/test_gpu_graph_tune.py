@@ -227,3 +227,34 @@ def test_fused_planes_with_graphs_and_partial_batches():
         junk = torch.randn(1 << 18, device="cuda").sum()
         assert torch.isfinite(junk)
     plan.close()
+
+
+@pytest.mark.gpu
+def test_pass_times_with_fused_and_separate_planes():
+    """Per-pass event timing: a pass fused into the previous one's kernel
+    reports zero, every other pass a positive time, over the calls made."""
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w = W.random_field((100, 70, 2), n_lines=1, batch=2, seed=27, d=(1.0, 1.0, 2.0))
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=32, batch=2)
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32).contiguous()
+    base = B.Plan(desc).info()
+    for yx, xy in ((2, 2), (1, 1), (2, 1)):
+        t = B.Tuning()
+        t.rows_x, t.tk_y, t.tk_z = base.rows_x, base.tile_y, base.tile_z
+        t.ex, t.ey, t.ez, t.z_groups, t.yx, t.xy = 16, 8, base.ez, base.z_groups, yx, xy
+        plan = B.Plan(desc, tuning=t)
+        out = plan.new_output()
+        plan.set_density(rho)
+        plan.set_profiling(True)
+        for _ in range(3):
+            plan.stress(out)
+        torch.cuda.synchronize()
+        ms, calls = plan.pass_times()
+        ms = [ms[k] for k in ("x_r2c", "y_fwd", "z_fused", "y_inv", "x_c2r")] if isinstance(ms, dict) else list(ms)
+        assert calls == 3
+        assert ms[0] > 0 and ms[2] > 0 and ms[3] > 0
+        assert (ms[1] == 0) == (xy == 2) and (ms[4] == 0) == (yx == 2)
+        assert all(v > 0 for i, v in enumerate(ms) if not ((i == 1 and xy == 2) or (i == 4 and yx == 2)))
+        plan.set_profiling(False)
+        plan.close()
