@@ -153,6 +153,8 @@ def test_tuning_outside_limits_is_rejected():
                                            # more planes than resident blocks (288 forward, 576
                                            # inverse): blocks walk on to further planes
                                            ((120, 100, 48), (False, False)),
+                                           # odd rows (unpaired loads and stores), smallest fused planes
+                                           ((65, 65, 48), (False, False)),
                                            # periodic x: full-length rows (no zero upper half)
                                            ((256, 72, 48), (True, False))])
 def test_fused_inverse_yx_gives_separate_bits(grid, periodic):
