@@ -312,7 +312,7 @@ __device__ __forceinline__ void load_tw_stages(cplx<T> (&w)[TWC], int j, const c
 // one before the writes of each stage serve all K, whose exchanges use the LDS
 // regions lds + k * region. HZ: inputs m >= E/2 of every transform are zero
 // (zero-padded data) and are not read. Threads with act == false (whole
-// waves) take part in the barriers without touching LDS.
+// waves) take part in the barriers without touching LDS or computing.
 template <typename T, int N, int E, bool FWD, bool HZ, int Ns, int R, int KT, int K, int TWC, class Lay>
 __device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
                                            Lay lay, int c, int j, bool act) {
@@ -339,17 +339,19 @@ __device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (
                     for (int r = 0; r < R; ++r) v[k][q][r] = lds[k * region + lay(j + Tc * q + r * (N / R), c)];
         }
     }
+    if (act) {          // idle waves skip the arithmetic too
 #pragma unroll
-    for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            if constexpr (!first) {
+            for (int q = 0; q < NB; ++q) {
+                if constexpr (!first) {
 #pragma unroll
-                for (int r = 1; r < R; ++r) v[k][q][r] = twmul<FWD>(v[k][q][r], w[KT + q * (R - 1) + r - 1]);
+                    for (int r = 1; r < R; ++r) v[k][q][r] = twmul<FWD>(v[k][q][r], w[KT + q * (R - 1) + r - 1]);
+                }
+                if constexpr (first && HZ) dftR_hz<R, FWD>(v[k][q]);
+                else dftR<R, FWD>(v[k][q]);
             }
-            if constexpr (first && HZ) dftR_hz<R, FWD>(v[k][q]);
-            else dftR<R, FWD>(v[k][q]);
-        }
+    }
     if constexpr (last) {
 #pragma unroll
         for (int k = 0; k < K; ++k)

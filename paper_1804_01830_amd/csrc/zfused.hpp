@@ -110,6 +110,20 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
     T* s_l = reinterpret_cast<T*>(smem_raw + (size_t)N * ld * sizeof(cplx<T>));
     const T* s_lj = s_l + j * KS + c;               // staged row kz = j of this lane
     const T* s_lm = s_l + (Tc - j) * KS + c;        // staged row kz = Tc - j (mirrored elements)
+    // Staged row of each element: kz = j + Tc m, or with a z mirror, for the
+    // upper half, its mirror row (Tc - j) + Tc (E - 1 - m). The mirror choice is
+    // made once per element and hidden from the optimiser: left visible, it
+    // became one selected address per element and read (about 70 registers held
+    // across the realisations, which spilled) instead of an immediate offset.
+    int s_row[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        s_row[m] = j * KS + c + Tc * m * KS;
+        if (2 * m >= E) {
+            s_row[m] = zc ? (Tc - j) * KS + c + Tc * (E - 1 - m) * KS : s_row[m];
+            asm volatile("" : "+v"(s_row[m]));
+        }
+    }
     if constexpr (SL) {
         // copy [c][v][kz][TK] -> rows kz of [c][v][TK] in 16-byte pieces: up to
         // 16 loads per thread are in flight before their stores; a piece never
@@ -155,14 +169,18 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
             const int base_ = ((CH) * 6 + v) * nkz;                                        \
             _Pragma("unroll") for (int m = 0; m < E; ++m) {                                \
                 const bool mir_ = zc && (2 * m >= E);      /* uniform: selects, no branch */ \
-                if constexpr (SL)                                                          \
-                    DST[v][m] = mir_ ? s_lm[(Tc * (E - 1 - m)) * KS + ((CH) * 6 + v) * TK] \
-                                     : s_lj[(Tc * m) * KS + ((CH) * 6 + v) * TK];          \
-                else                                                                       \
-                    DST[v][m] = buf_real<T>(srs, mir_ ? s_lane_m : s_lane,                 \
-                                            (base_ + (mir_ ? Tc * (E - 1 - m) : Tc * m)) * tk * (int)sizeof(T)); \
+                DST[v][m] = buf_real<T>(srs, mir_ ? s_lane_m : s_lane,                     \
+                                        (base_ + (mir_ ? Tc * (E - 1 - m) : Tc * m)) * tk * (int)sizeof(T)); \
             }                                                                              \
         }                                                                                  \
+    }
+// Staged values: element m of this lane reads row offset s_row[m] (mirrored
+// or not) plus an immediate per (channel, component).
+#define DDS_LOAD_SPEC_SL(DST, CH)                                                          \
+    {                                                                                      \
+        _Pragma("unroll") for (int v = 0; v < 6; ++v)                                      \
+            _Pragma("unroll") for (int m = 0; m < E; ++m)                                  \
+                DST[v][m] = s_l[s_row[m] + ((CH) * 6 + v) * TK];                           \
     }
 
     T sv[6][E];
@@ -185,7 +203,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
                 // staged values are read from LDS here, after the transform (they
                 // need no registers while it runs); values from memory were
                 // requested before it
-                if constexpr (SL) DDS_LOAD_SPEC(sv, ch)
+                if constexpr (SL) DDS_LOAD_SPEC_SL(sv, ch)
 #pragma unroll
                 for (int v = 0; v < 6; ++v) {
                     // signs of mirrored spectrum rows (wave-uniform); staged
@@ -214,6 +232,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
         }
 #undef DDS_LOAD_RHO
 #undef DDS_LOAD_SPEC
+#undef DDS_LOAD_SPEC_SL
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             fft_regs_k<T, N, E, false, false, 1>(acc[v], twr, lds, 0, lay, c, j);
