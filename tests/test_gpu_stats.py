@@ -81,7 +81,8 @@ def test_flat_grains_standard_deviation_does_not_depend_on_grain_size():
     assert abs(slope) < 0.3
 
 
-@pytest.mark.parametrize("case", ["fp32-fused-planes", "fp32-passes", "fp64", "fp32-periodic"])
+@pytest.mark.parametrize("case", ["fp32-fused-planes", "fp32-fused-many-planes", "fp32-passes", "fp64",
+                                  "fp32-periodic"])
 def test_plane_statistics_fused_into_the_stress_call(case):
     """Eq. (20) from the inverse x pass's epilogue against the standalone
     reduction of the written stress: equal up to summation order (1e-13),
@@ -89,6 +90,8 @@ def test_plane_statistics_fused_into_the_stress_call(case):
     import torch
     from paper_1804_01830_amd import binding as B
     shape, prec, periodic = {"fp32-fused-planes": ((100, 70, 2), 32, (False, False)),
+                             # 3 x 6 x 16 = 288 inverse planes: blocks walk on to further planes
+                             "fp32-fused-many-planes": ((100, 70, 16), 32, (False, False)),
                              "fp32-passes": ((20, 12, 5), 32, (False, False)),
                              "fp64": ((20, 12, 5), 64, (False, False)),
                              "fp32-periodic": ((32, 16, 4), 32, (True, True))}[case]
@@ -96,7 +99,7 @@ def test_plane_statistics_fused_into_the_stress_call(case):
     desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=prec, batch=3, periodic=periodic,
                        pbc_shells=2)
     plan = B.Plan(desc)
-    if case == "fp32-fused-planes":
+    if case.startswith("fp32-fused"):
         assert plan.info().yx_fused == 1
     dt = torch.float32 if prec == 32 else torch.float64
     rho = torch.from_numpy(w["rho"]).to("cuda", dtype=dt).contiguous()
