@@ -582,7 +582,7 @@ def main():
             graph = dict(wall=gw, per=gper)
             hw, hper, hbytes = time_host_io(plan, rho, min(steps, 50), min(args.warmup, 5))
             host = dict(wall=hw, per=hper, bytes=hbytes, steps=min(steps, 50))
-        stats_ms = fused_ms = None
+        stats_ms = fused_ms = plain_ms = None
         if prec == 32 and args.workload == "sweep-64":
             grain_law = sweep_grain_law(w, plan, out)
         if prec == 32:
@@ -596,14 +596,17 @@ def main():
             e1.record(stream)
             torch.cuda.synchronize()
             stats_ms = e0.elapsed_time(e1) / 20
-            # the same statistics fused into the stress call (inverse x epilogue)
+            # the same statistics fused into the stress call (inverse x epilogue),
+            # against the same unprofiled loop without them
+            pw, _, _, _ = time_path(plan, rho, out, min(steps, 100), min(args.warmup, 10), profile=False)
             plan.set_plane_stats(ms_out)
             fw, fper, _, _ = time_path(plan, rho, out, min(steps, 100), min(args.warmup, 10), profile=False)
             plan.set_plane_stats(None)
             fused_ms = fw / min(steps, 100) * 1e3
+            plain_ms = pw / min(steps, 100) * 1e3
         info = plan.info()
         res[prec] = dict(plan=plan, info=info, wall=wall, per=per, passes=passes, calls=calls, steps=steps,
-                         stats_ms=stats_ms, fused_ms=fused_ms, nye_ms=nye_ms,
+                         stats_ms=stats_ms, fused_ms=fused_ms, plain_ms=plain_ms, nye_ms=nye_ms,
                          grain_law=grain_law if (prec == 32 and args.workload == "sweep-64") else None,
                          plan_s=plan_s, graph=graph, host=host, tune=Tn.to_dict(tune) if tune is not None else None,
                          out=out[0].double().cpu().numpy() if (B == 1 or plain_one) else None,
@@ -673,7 +676,9 @@ def main():
                         "ms": round(r32["stats_ms"], 5),
                         "gbs": round(B * 6 * nx * ny * nz * 4 / (r32["stats_ms"] * 1e-3) / 1e9, 1),
                         "fused_ms_per_step": round(r32["fused_ms"], 5),
-                        "fused_note": "stress call with the statistics in the inverse x pass (ddstress_plan_set_plane_stats)"},
+                        "plain_ms_per_step": round(r32["plain_ms"], 5),
+                        "fused_note": "stress call with the statistics in the inverse x pass (ddstress_plan_set_plane_stats), "
+                                      "and the same loop without them; both without per-pass events"},
         "roofline": roofline,
         "plan_info": plan_info,
     }

@@ -272,7 +272,7 @@ ddstress_status ddstress_kernel_realspace(const ddstress_desc* desc, int32_t lin
  * sigma[b][v][k][j][i]^2 (Eq. 20; as ddstress_plane_mean_square, summed in
  * another fixed order), computed in the inverse x pass from the values it
  * writes (no second read of sigma): one FP64 sum of squares per row, then
- * the rows of each plane in order. stats: device buffer of batch * 6 * Nz
+ * the rows of each plane in a fixed order. stats: device buffer of batch * 6 * Nz
  * doubles, kept by the caller while set. The first non-NULL call allocates
  * batch * 6 * Nz * Ny doubles of row sums for the plan's lifetime; NULL
  * switches the statistics off. Drops the plan's captured graphs. */

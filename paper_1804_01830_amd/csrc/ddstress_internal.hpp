@@ -133,7 +133,7 @@ __device__ __forceinline__ void row_square_sum(const cplx<T>* reg, int j, int n_
     if (j == 0) *dst = sq;
 }
 // Plane statistics from row sums: out[p] = inv * sum_{y < ny} rowsq[p ny + y]
-// (in order), for planes p < nplanes (stats.hip).
+// (in a fixed order), for planes p < nplanes (stats.hip).
 void launch_rowsq_finish(const double* rowsq, int64_t nplanes, int ny, double inv, double* out, hipStream_t s);
 // Complex transform of length N along a strided axis, on tiles of consecutive columns.
 struct ColGeom {

@@ -4,7 +4,7 @@
 // then a tree over the block), so the result does not depend on anything
 // but the input. Reads the stress once: an HBM-bound reduction. Fused with
 // the stress call: the inverse x pass leaves one sum of squares per row and
-// k_rowsq_finish adds the rows of each plane in order.
+// k_rowsq_finish adds the rows of each plane in a fixed order.
 #include "ddstress_internal.hpp"
 
 namespace dds {
@@ -41,22 +41,30 @@ __global__ void __launch_bounds__(kStatThreads)
     if (t == 0) out[blockIdx.x] = red[0] * inv_plane;
 }
 
+// One wave per plane (four per block): lane l adds rows l, l + 64, ... in
+// order (consecutive lanes read consecutive rows), then the 64 partial sums
+// are combined by a butterfly; the order is fixed, so every call gives the
+// same bits.
 __global__ void __launch_bounds__(256) k_rowsq_finish(const double* __restrict__ rowsq, int64_t nplanes, int ny,
                                                       double inv, double* __restrict__ out) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nplanes) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t p = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= nplanes) return;           // whole waves: the butterfly below has every lane
     const double* r = rowsq + p * ny;
     double s = 0.0;
-    for (int y = 0; y < ny; ++y) s += r[y];
-    out[p] = s * inv;
+    for (int y = lane; y < ny; y += 64) s += r[y];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) out[p] = s * inv;
 }
 
 }  // namespace
 
 void launch_rowsq_finish(const double* rowsq, int64_t nplanes, int ny, double inv, double* out, hipStream_t s) {
     if (nplanes <= 0) return;
-    hipLaunchKernelGGL(k_rowsq_finish, dim3((unsigned)((nplanes + 255) / 256)), dim3(256), 0, s, rowsq, nplanes, ny,
-                       inv, out);
+    if ((nplanes + 3) / 4 > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "too many planes for one launch");
+    hipLaunchKernelGGL(k_rowsq_finish, dim3((unsigned)((nplanes + 3) / 4)), dim3(256), 0, s, rowsq, nplanes, ny, inv,
+                       out);
     check_hip(hipGetLastError(), "plane statistics finish launch");
 }
 
