@@ -179,7 +179,9 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
             }
             if (rowsq) row_square_sum<T, EX, TCX>(reg, jx, nx, rowsq + plane * (int64_t)ny + y);
         }
-        __syncthreads();                             // the x exchanges are done before the next plane's columns
+        // (no barrier here: the next plane's first LDS write follows the barrier
+        // inside its first transform stage, which every thread reaches only
+        // after this plane's reads)
     }
 }
 
@@ -325,7 +327,8 @@ __global__ void __launch_bounds__(kYXThreads) k_xy_fwd(const float* __restrict__
             }
             c0 += ncols;
         }
-        __syncthreads();                             // the last exchanges are read before the next plane's rows
+        // (no barrier here: the next plane's first LDS write follows the barrier
+        // inside its first row-transform stage)
     }
 }
 
