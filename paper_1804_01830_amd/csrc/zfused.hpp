@@ -108,8 +108,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
     load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
 
     T* s_l = reinterpret_cast<T*>(smem_raw + (size_t)N * ld * sizeof(cplx<T>));
-    const T* s_lj = s_l + j * KS + c;               // staged row kz = j of this lane
-    const T* s_lm = s_l + (Tc - j) * KS + c;        // staged row kz = Tc - j (mirrored elements)
     // Staged row of each element: kz = j + Tc m, or with a z mirror, for the
     // upper half, its mirror row (Tc - j) + Tc (E - 1 - m). The mirror choice is
     // made once per element and hidden from the optimiser: left visible, it
