@@ -74,7 +74,12 @@ typedef enum {
 } ddstress_where;
 
 /* Problem statement: grid, cell sizes, elastic constants, line directions.
- * Limits: 1 <= N_a <= 512 on every axis; 1 <= n_lines <= 3; batch >= 1. */
+ * Limits: 1 <= N_a <= 512 on every axis; 1 <= n_lines <= 3; batch >= 1; and
+ * (Pz / 2) Py Wx complex values of the plan precision span at most 2^31 - 1
+ * bytes, with Wx = (Px / 2 + 1) rounded up to a multiple of 16 (the z pass
+ * addresses one density plane with 32-bit offsets): with Px = Py = 1024 this
+ * holds up to Nz = 256 in FP32 and Nz = 128 in FP64; larger grids are
+ * DDSTRESS_E_UNSUPPORTED. */
 typedef struct {
     int32_t n[3];          /* Nx, Ny, Nz (x fastest in memory) */
     double  d[3];          /* dx, dy, dz > 0, same length unit as 1/rho */
@@ -177,7 +182,10 @@ ddstress_status ddstress_plan_footprint(const ddstress_desc* desc, size_t* cache
  * them with an FP64 3D FFT and keeps the spectrum (purely imaginary because K
  * is odd) in the plan precision. Work runs on `stream`; the call returns after
  * the build has completed (it synchronises the stream). On success *out owns
- * device memory until ddstress_plan_destroy. */
+ * device memory until ddstress_plan_destroy. A transform whose real part
+ * exceeds 1e-13 of its imaginary part (max over the kept wavevectors; for a
+ * kernel that cancels to rounding, 1e-13 mu min(d)) fails with
+ * DDSTRESS_E_UNSUPPORTED: only Im K^ is kept. */
 ddstress_status ddstress_plan_create(const ddstress_desc* desc, void* stream, ddstress_plan* out);
 
 /* Autotuner: times every admissible tile size, element class and z group
@@ -195,19 +203,40 @@ ddstress_status ddstress_plan_create_tuned(const ddstress_desc* desc, const ddst
                                            ddstress_plan* out);
 
 /* Hand the B densities [B][C][Nz][Ny][Nx] (plan precision) to the plan.
- * HOST and DEVICE_COPY enqueue a copy on `stream` (the caller may reuse rho
- * once the stream has passed that point; host memory should be pinned for the
- * copy to be asynchronous); DEVICE_BORROW records the pointer only. */
+ * Defined by Sec. 2.1, Eq. (3b): the stress of the whole sample is the sum
+ * over dislocation types of the density n times the Burgers vector b times
+ * the interaction function, and f is linear in b, so the density of type
+ * (t_l, b) enters as the three channels rho_{3l+gamma} = n b_gamma (unit
+ * length^-1), cell (i, j, k) holding the value at its centre (i dx, j dy, k dz).
+ * rho: B realisations, C = 3L channels each, x fastest, contiguous.
+ * Ownership: HOST and DEVICE_COPY enqueue a copy on `stream` into a buffer the
+ * plan owns (the caller may reuse rho once the stream has passed that point;
+ * host memory should be pinned for the copy to be asynchronous);
+ * DEVICE_BORROW records the pointer only, and the caller keeps the buffer
+ * alive and unchanged until the stress calls that read it have completed.
+ * Errors: DDSTRESS_E_INVALID for a NULL plan or rho or an unknown `where`;
+ * DDSTRESS_E_NOMEM if the plan's density buffer cannot be allocated (first
+ * copying call); DDSTRESS_E_DEVICE if the copy cannot be enqueued. */
 ddstress_status ddstress_set_density(ddstress_plan plan, const void* rho, int32_t where, void* stream);
 
-/* Enqueue the stress evaluation of the current densities on `stream`:
- * forward x (real-to-complex), y and z transforms of the zero-padded density
- * channels, the per-wavevector contraction with the kernel spectrum, inverse
- * z, y and x (complex-to-real) transforms cropped to the grid.
- * `sigma` is [B][6][Nz][Ny][Nx] in the plan precision; `where` is DDSTRESS_HOST
- * (written through an internal device buffer and an asynchronous copy) or
- * DDSTRESS_DEVICE_COPY / DDSTRESS_DEVICE_BORROW (both: written in place).
- * DDSTRESS_E_STATE if no density was set. */
+/* Enqueue the stress evaluation of the current densities on `stream`.
+ * Defined by Sec. 2.3, Eq. (10): for every cell r0,
+ *     sigma_v(r0) = sum_{cells i} sum_c K_{v,c}(r0 - r_i) rho_c(r_i),
+ * a discrete linear convolution, evaluated by the convolution theorem on the
+ * grid zero-padded to P_a >= 2 N_a - 1 per open axis (no wrap-around):
+ * forward x (real-to-complex), y and z transforms of the density channels,
+ * the per-wavevector contraction sigma^_v = sum_c K^_{v,c} rho^_c with the
+ * plan's kernel spectrum (c in increasing order), inverse z, y and x
+ * (complex-to-real) transforms cropped to the grid.
+ * sigma: [B][6][Nz][Ny][Nx] in the plan precision, Voigt order (xx, yy, zz,
+ * yz, xz, xy), unit of mu, x fastest, contiguous; owned by the caller.
+ * `where` is DDSTRESS_HOST (written through a plan-owned device buffer and an
+ * asynchronous copy: host memory should be pinned) or DDSTRESS_DEVICE_COPY /
+ * DDSTRESS_DEVICE_BORROW (both: written in place on the device).
+ * Errors: DDSTRESS_E_INVALID for a NULL plan or sigma or an unknown `where`;
+ * DDSTRESS_E_STATE if no density was set; DDSTRESS_E_NOMEM if the staging
+ * buffer of a HOST output cannot be allocated; DDSTRESS_E_DEVICE if a launch
+ * or copy cannot be enqueued. */
 ddstress_status ddstress_stress(ddstress_plan plan, void* sigma, int32_t where, void* stream);
 
 /* A second plan of the same geometry (grid, cells, constants, lines,

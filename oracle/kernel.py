@@ -41,12 +41,16 @@ from .segment import segment_stress, chord_length
 @dataclass(frozen=True)
 class KernelGeometry:
     """Cell sizes ``d`` = (dx, dy, dz), elastic constants, one line direction
-    ``t`` and the number of near shells. All lengths in one unit."""
+    ``t`` and the number of near shells. All lengths in one unit. ``refine``
+    multiplies the subcell count on every axis (1: the subdivision described
+    above); the subcells stay as near-cubic as the plain ones, so raising it
+    only refines the near-cell sums (used to check their convergence)."""
     d: tuple
     t: tuple
     mu: float
     nu: float
     near_shells: int = 2
+    refine: int = 1
 
     @property
     def unit_t(self):
@@ -57,7 +61,7 @@ class KernelGeometry:
     def subdivision(self):
         d = np.asarray(self.d, dtype=np.float64)
         dmin = d.min()
-        return np.array([max(1, int(np.floor(d[a] / dmin + 0.5))) for a in range(3)])
+        return np.array([max(1, int(np.floor(d[a] / dmin + 0.5))) * int(self.refine) for a in range(3)])
 
     @property
     def sub_box(self):

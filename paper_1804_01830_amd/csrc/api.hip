@@ -117,6 +117,13 @@ Shape make_shape(const ddstress_desc* d) {
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
     set_mirrors(s, predict_mirror(d, 1), predict_mirror(d, 2));
     s.sgn_y = s.sgn_z = 0;
+    // The fused z pass addresses a density plane [Nz][Py][Wx] through one
+    // buffer resource with 32-bit byte offsets: every row it can form (z <
+    // Pz/2) must lie within a signed 32-bit offset.
+    const int64_t zrow_bytes = (int64_t)s.P[1] * s.wx * 2 * s.elem;
+    if ((int64_t)(s.P[2] / 2) * zrow_bytes > (int64_t)INT32_MAX)
+        fail(DDSTRESS_E_UNSUPPORTED, "grid too large for the z pass's 32-bit plane offsets: Pz/2 * Py * Wx complex "
+                                     "values (" + std::to_string((s.P[2] / 2) * zrow_bytes) + " bytes) exceed 2^31 - 1");
     return s;
 }
 
@@ -331,6 +338,21 @@ void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
     std::memcpy(&im, &bits[1], sizeof(double));
     p->re_max = re;
     p->im_max = im;
+    // K is odd, so K^ is purely imaginary and only Im K^ is kept: a real part
+    // above the rounding of the FP64 transforms would be dropped silently. The
+    // scale is max |Im K^|, or, for a kernel that cancels to rounding (a
+    // period of two cells on every in-plane axis and one layer), mu min(d),
+    // the size of one near-cell coefficient up to a factor of order one.
+    const double dmin = std::min(p->desc.d[0], std::min(p->desc.d[1], p->desc.d[2]));
+    const double scale = std::max(im, p->desc.mu * dmin);
+    if (!(re <= 1e-13 * scale)) {
+        char msg[256];
+        std::snprintf(msg, sizeof(msg),
+                      "kernel spectrum is not purely imaginary (max |Re K^| = %.3e, max |Im K^| = %.3e): the plan "
+                      "keeps Im K^ only, which needs an odd kernel",
+                      re, im);
+        fail(DDSTRESS_E_UNSUPPORTED, msg);
+    }
 }
 
 template <typename T>

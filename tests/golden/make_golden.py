@@ -38,6 +38,8 @@ def _targets(n, count, seed):
 FIXTURES = {
     # 256 x 256 x 64 columnar polycrystal, edge and 15.6-degree mixed lines, nu = 0.2
     "poly_layer_256x256x64": dict(gen="poly_layer", kwargs={}, batch_index=0, targets=10, seed=31),
+    # the largest served shape: 256 x 256 x 128 (z transforms of length 256)
+    "poly_layer_256x256x128": dict(gen="poly_layer", kwargs={"nz": 128}, batch_index=0, targets=10, seed=51),
     # two realisations of the 64-realisation sweep (grain sizes 4 and 32 cells)
     "poly_sweep_128x128x32_b0": dict(gen="poly_sweep", kwargs={}, batch_index=0, targets=6, seed=41),
     "poly_sweep_128x128x32_b63": dict(gen="poly_sweep", kwargs={}, batch_index=63, targets=6, seed=42),

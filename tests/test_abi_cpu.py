@@ -129,3 +129,23 @@ def test_relaxation_solve_rejects_bad_arguments_without_a_plan():
     import ctypes
     steps, norm = ctypes.c_int32(), ctypes.c_double()
     assert lib.ddstress_relax_solve(None, 1e-6, 10, 1, ctypes.byref(steps), ctypes.byref(norm), None) == B.E_INVALID
+
+
+@pytest.mark.parametrize("n,precision,ok", [
+    ((512, 512, 256), 32, True), ((512, 512, 257), 32, False),
+    ((512, 512, 128), 64, True), ((512, 512, 129), 64, False), ((257, 257, 129), 64, False),
+    ((512, 256, 512), 32, True), ((256, 512, 512), 64, False),
+])
+def test_z_pass_offsets_are_bounded(n, precision, ok):
+    """The fused z pass addresses one density plane [Nz][Py][Wx] with 32-bit
+    byte offsets; a grid whose rows z < Pz/2 would need more is refused with
+    DDSTRESS_E_UNSUPPORTED before anything is allocated (a larger plane would
+    wrap the offsets and read wrong rows)."""
+    desc = _desc(n=n, precision=precision)
+    if ok:
+        B.footprint(desc)
+        return
+    with pytest.raises(B.DDStressError) as e:
+        B.footprint(desc)
+    assert e.value.status == B.E_UNSUPPORTED
+    assert "32-bit" in B.load().ddstress_last_error().decode()

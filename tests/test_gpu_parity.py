@@ -243,3 +243,125 @@ def test_grouped_long_z_classes(precision, lines):
     comp, whole = rel_l2(out.double().cpu().numpy(), ref)
     assert np.all(comp <= TOL[precision]) and whole <= TOL[precision]
     plan.close()
+
+
+# z transforms of length 256 (Nz 65..128) and 512 (Nz 129..256): every
+# admissible fused z form (single-group and grouped, every element class and
+# tile width that fits), including the staged spectrum of the single-group form
+# (B >= 2, z lengths up to 256), against the direct sum.
+LONG_Z = {
+    "rand-9x7x100-L1-B3": lambda: W.random_field((9, 7, 100), n_lines=1, batch=3, seed=31, d=(1.0, 1.0, 2.0)),
+    "rand-6x5x90-L2-B2": lambda: W.random_field((6, 5, 90), n_lines=2, batch=2, seed=32, d=(1.0, 1.0, 2.0)),
+    "rand-5x4x200-L1-B2": lambda: W.random_field((5, 4, 200), n_lines=1, batch=2, seed=33),
+    "rand-4x3x150-L3": lambda: W.random_field((4, 3, 150), n_lines=3, seed=34, d=(1.0, 1.5, 2.0)),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _long_case(name):
+    w = LONG_Z[name]()
+    ref = np.stack([stress_direct(w["rho"][b], w["d"], w["lines"], w["mu"], w["nu"])
+                    for b in range(w["rho"].shape[0])])
+    return w, ref
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("name", list(LONG_Z))
+def test_long_z_every_form(name, precision):
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w, ref = _long_case(name)
+    nb = w["rho"].shape[0]
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision, batch=nb)
+    base = B.Plan(desc)
+    d0 = base.info()
+    base.close()
+    Pz, C = d0.padded[2], d0.channels
+    assert Pz in (256, 512)
+    dt = torch.float32 if precision == 32 else torch.float64
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=dt).contiguous()
+    b0 = 4 if precision == 32 else 2
+    ran = []
+    for groups in (1, C):
+        for ez in (b0, 2 * b0, 4 * b0, 8 * b0):
+            if ez > 16:
+                continue
+            for tk in (1, 2, 4, 8, 16):
+                t = B.Tuning()
+                t.rows_x, t.tk_y, t.ex, t.ey = d0.rows_x, d0.tile_y, d0.ex, d0.ey
+                t.tk_z, t.ez, t.z_groups = tk, ez, groups
+                try:
+                    plan = B.Plan(desc, tuning=t)
+                except B.DDStressError as e:
+                    assert e.status == B.E_INVALID
+                    continue
+                _say(f"[long-z] {name} precision={precision} Pz={Pz} groups={groups} ez={ez} tk={tk}")
+                plan.set_density(rho)
+                out = plan.new_output()
+                plan.stress(out)
+                torch.cuda.synchronize()
+                got = out.double().cpu().numpy()
+                plan.close()
+                comp, whole = rel_l2(got, ref)
+                assert np.all(comp <= TOL[precision]) and whole <= TOL[precision], (groups, ez, tk, comp, whole)
+                ran.append((groups, ez, tk))
+    _say(f"  {len(ran)} forms: {ran}")
+    assert any(g == 1 for g, _, _ in ran)
+    assert len({e for _, e, _ in ran}) >= 2            # a longer element class ran too
+    if C <= 6 and (precision == 32 or C == 3):
+        assert any(g == C for g, _, _ in ran)          # the grouped form fits here
+
+
+@pytest.mark.parametrize("precision", [32, 64])
+def test_poly_layer_256x256x128_golden(precision):
+    """The largest served shape, 256 x 256 x 128 (Pz = 256, Px = Py = 512),
+    FP32 through an autotuned plan (the launch shapes the server and the
+    benchmark use) and FP64 with the default shapes, against stored oracle
+    values at 10 cells."""
+    import torch
+    from paper_1804_01830_amd import binding as B
+    from paper_1804_01830_amd import tuning as Tn
+    g = _load_golden("poly_layer_256x256x128")
+    w = W.poly_layer(nz=128)
+    assert list(w["n"]) == g["n"] and np.allclose(w["lines"], g["lines"])
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision)
+    tune = Tn.get_tuning(desc) if precision == 32 else None
+    plan = B.Plan(desc, tuning=tune)
+    info = plan.info()
+    _say(f"[poly-layer-256x256x128] precision={precision} padded={tuple(info.padded)} tile_z={info.tile_z} "
+         f"ez={info.ez} z_groups={info.z_groups}")
+    dt = torch.float32 if precision == 32 else torch.float64
+    plan.set_density(torch.from_numpy(w["rho"]).to("cuda", dtype=dt))
+    out = plan.new_output()
+    plan.stress(out)
+    torch.cuda.synchronize()
+    tg = np.array(g["targets"])
+    got = out[0][:, tg[:, 2], tg[:, 1], tg[:, 0]].double().cpu().numpy()
+    plan.close()
+    comp, whole = rel_l2(got, np.array(g["sigma_voigt"]).T)
+    _say(f"  per component {np.array2string(comp, precision=2)} whole {whole:.2e}")
+    assert np.all(comp <= TOL[precision]) and whole <= TOL[precision]
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=(128, 128, 32), d=(1.0, 1.0, 2.0), lines=[(0.0, 0.0, 1.0)]),
+    dict(n=(256, 256, 64), d=(1.0, 1.0, 2.0), lines=[(0.0, 0.0, 1.0), TILT]),
+    dict(n=(20, 14, 10), d=(1.0, 1.5, 2.0), lines=[DIAG, TILT, (1.0, 0.0, 0.0)]),
+    dict(n=(64, 64, 16), d=(1.0, 1.0, 2.0), lines=[(0.0, 0.0, 1.0), TILT], periodic=(True, True)),
+    dict(n=(2, 2, 512), d=(1.0, 1.0, 1.0), lines=[(0.0, 0.0, 1.0)]),
+])
+def test_kernel_spectrum_is_imaginary(case):
+    """K is odd (K(-D) = -K(D), Sec. 2.3 with the symmetric subdivision), so
+    its transform is purely imaginary and the plan keeps Im K^ only; the real
+    part it measures while building must be rounding-level (plan creation
+    checks the same bound and would refuse the plan otherwise)."""
+    from paper_1804_01830_amd import binding as B
+    desc = B.make_desc(case["n"], case["d"], 1.0, 0.3, case["lines"], precision=64,
+                       periodic=case.get("periodic", (False, False)))
+    plan = B.Plan(desc)
+    info = plan.info()
+    plan.close()
+    ratio = info.kernel_real_max / info.kernel_imag_max
+    _say(f"[spectrum] n={case['n']} periodic={case.get('periodic')} max|Re|={info.kernel_real_max:.3e} "
+         f"max|Im|={info.kernel_imag_max:.3e} ratio={ratio:.2e}")
+    assert info.kernel_imag_max > 0.0 and ratio <= 1e-13

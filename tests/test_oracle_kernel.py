@@ -109,3 +109,47 @@ def test_kernel_scales_with_mu():
     b = KernelGeometry(d=(1.0, 1.0, 2.0), t=TILT, mu=3.0, nu=0.25)
     off = np.array([[1, 0, 0], [5, 5, 3]])
     assert np.allclose(3.0 * interaction_kernel(a, off), interaction_kernel(b, off), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("t", [(0, 0, 1), TILT])
+def test_near_cell_coefficients_converge_under_refinement(t):
+    """Sec. 2.3: the near-cell coefficient is the mean over target subcells of
+    the sum over source subcells, a midpoint-rule approximation of the
+    cell-averaged interaction; doubling the subcells per axis (m -> 2m -> 4m
+    -> 8m) must converge at second order: successive changes shrink about
+    fourfold. A wrong sub-offset weight, subcell chord or subcell volume
+    breaks the rate (the sums then tend to another limit or diverge)."""
+    offs = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0], [1, 0, 1], [2, 0, 0], [2, 1, 1], [-1, 2, -1]])
+    Ks = [interaction_kernel(KernelGeometry(d=(1.0, 1.0, 2.0), t=t, mu=MU, nu=NU, refine=f), offs)
+          for f in (1, 2, 4, 8)]
+    for i, o in enumerate(offs):
+        d = [np.abs(Ks[k][i] - Ks[k + 1][i]).max() for k in range(3)]
+        r = [d[0] / d[1], d[1] / d[2]]
+        assert 2.5 < r[0] < 5.5 and 2.8 < r[1] < 5.0, (o, d, r)
+
+
+def test_stress_converges_when_the_cells_are_halved():
+    """Sec. 2.3, last paragraph: halving the cell size must not change the
+    result noticeably. A smooth density blob (edge lines along z, b = e_x)
+    is sampled on grids with d = (1, 1, 2), (1/2, 1/2, 1) and (1/4, 1/4, 1/2)
+    over the same region; the stress at common physical points changes by
+    less than 3 % between the two finest grids, and successive changes fall
+    at second order (a missing cell volume would scale each level by 8)."""
+    from oracle.direct import stress_direct
+    d0 = np.array([1.0, 1.0, 2.0])
+    span = np.array([9.0, 9.0, 10.0])
+    c, w = span / 2, 1.6
+    tc = np.array([[5, 5, 2], [2, 5, 2], [5, 7, 3], [8, 1, 0], [4, 4, 4]])
+    res = []
+    for lev in range(3):
+        dd = d0 / 2 ** lev
+        n = [int(round(span[a] / dd[a])) + 1 for a in range(3)]
+        z, y, x = (np.arange(n[a]) * dd[a] for a in (2, 1, 0))
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        rho = np.zeros((3, n[2], n[1], n[0]))
+        rho[0] = np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / (2 * w * w))
+        res.append(stress_direct(rho, tuple(dd), [(0, 0, 1)], MU, NU, targets=tc * 2 ** lev))
+    d01 = np.linalg.norm(res[0] - res[1])
+    d12 = np.linalg.norm(res[1] - res[2])
+    assert d12 < 0.03 * np.linalg.norm(res[2])
+    assert 3.0 < d01 / d12 < 5.5
