@@ -148,7 +148,23 @@ def b_pass_bytes(C, B, elem):
     return elem * (13 * C + 24 * C / B + 78)
 
 
-def time_path(plan, rho, out, steps, warmup, profile, graph=False):
+def survey_z_bytes(C, B, cells, elem):
+    """Algorithmic HBM bytes of one fused z launch by the five-pass model:
+    per cell and realisation it reads the C density columns (4C reals: the
+    half spectrum of the padded x-y plane holds about 2N complex values per
+    channel) and writes the six stress columns (24 reals), and the kernel
+    spectrum, 6C reals at every one of the ~4N non-redundant wavevectors, is
+    read once per launch: s (4C + 24C/B + 24) per cell, over B cells per
+    grid cell. The mirror-compressed spectrum the plans store is smaller;
+    z_pass_bytes counts that."""
+    return elem * (4 * C + 24 * C / B + 24) * B * cells
+
+
+def time_steps(plan, rho, out, steps, warmup, graph=False):
+    """The headline timing: `warmup` untimed steps, then exactly `steps`
+    steps (density hand-over and stress call) between two synchronisations
+    (wall clock) and two events on the stream (device time). No per-pass or
+    per-step events are recorded inside."""
     import torch
     from paper_1804_01830_amd import binding as Bd
     stream = torch.cuda.current_stream()
@@ -156,26 +172,40 @@ def time_path(plan, rho, out, steps, warmup, profile, graph=False):
     for _ in range(warmup):
         plan.set_density(rho, Bd.DEVICE_BORROW)
         plan.stress(out)
-    torch.cuda.synchronize()
-    if profile:
-        plan.set_profiling(True)
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
+    e0.record(stream)
+    for _ in range(steps):
+        plan.set_density(rho, Bd.DEVICE_BORROW)
+        plan.stress(out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.set_graph(False)
+    return wall, e0.elapsed_time(e1)
+
+
+def time_latency(plan, rho, out, reps, graph=False):
+    """Device time of `reps` single evaluations, each between its own pair
+    of events (p50 / p99 of one evaluation); sorted milliseconds."""
+    import torch
+    from paper_1804_01830_amd import binding as Bd
+    stream = torch.cuda.current_stream()
+    plan.set_graph(graph)
+    plan.set_density(rho, Bd.DEVICE_BORROW)
+    plan.stress(out)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(reps)]
+    torch.cuda.synchronize()
+    for i in range(reps):
         starts[i].record(stream)
         plan.set_density(rho, Bd.DEVICE_BORROW)
         plan.stress(out)
         ends[i].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
-    passes, calls = plan.pass_times() if profile else ({}, 0)
-    if profile:
-        plan.set_profiling(False)
     plan.set_graph(False)
-    return wall, per, passes, calls
+    return sorted(a.elapsed_time(b) for a, b in zip(starts, ends))
 
 
 def time_host_io(plan, rho, steps, warmup):
@@ -506,6 +536,10 @@ def main():
                     help="realisations per FP32 call for the disk-mixed workload (the FP64 plain path "
                          "always evaluates the single base grid)")
     ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--latency-reps", type=int, default=200,
+                    help="single evaluations with an event pair each, for p50 / p99 (at least --steps)")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="skip the 256x256x64 layer and the 64-realisation sweep after the default workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes for the FP32 plan")
@@ -556,135 +590,26 @@ def main():
         print(f"[bench] cpu baseline: {base['sample']}", file=sys.stderr, flush=True)
 
     import torch
-    from paper_1804_01830_amd import binding as Bd
     torch.cuda.set_device(0)
-
-    from paper_1804_01830_amd import tuning as Tn
-    res = {}
-    for prec in (32, 64):
-        Bp = 1 if (prec == 64 and plain_one) else B
-        desc = Bd.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=prec, batch=Bp,
-                            periodic=periodic)
-        t = time.perf_counter()
-        tune = None
-        if prec == 32 and not args.no_tune:
-            tune = Tn.get_tuning(desc)
-        plan = Bd.Plan(desc, tuning=tune)
-        plan_s = time.perf_counter() - t
-        dt = torch.float32 if prec == 32 else torch.float64
-        rho, nye_ms = device_density(w, Bp, dt)
-        out = plan.new_output()
-        steps = args.steps if prec == 32 else (args.fp64_steps or max(10, args.steps // 2))
-        wall, per, passes, calls = time_path(plan, rho, out, steps, args.warmup, profile=True)
-        graph = host = None
-        if prec == 32:
-            gw, gper, _, _ = time_path(plan, rho, out, steps, args.warmup, profile=False, graph=True)
-            graph = dict(wall=gw, per=gper)
-            hw, hper, hbytes = time_host_io(plan, rho, min(steps, 50), min(args.warmup, 5))
-            host = dict(wall=hw, per=hper, bytes=hbytes, steps=min(steps, 50))
-        stats_ms = fused_ms = plain_ms = None
-        if prec == 32 and args.workload == "sweep-64":
-            grain_law = sweep_grain_law(w, plan, out)
-        if prec == 32:
-            # Eq. (20) plane statistics of the stress just computed (one read of sigma)
-            stream = torch.cuda.current_stream()
-            ms_out = Bd.plane_mean_square(out)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(20):
-                Bd.plane_mean_square(out, ms_out)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            stats_ms = e0.elapsed_time(e1) / 20
-            # the same statistics fused into the stress call (inverse x epilogue),
-            # against the same unprofiled loop without them
-            pw, _, _, _ = time_path(plan, rho, out, min(steps, 100), min(args.warmup, 10), profile=False)
-            plan.set_plane_stats(ms_out)
-            fw, fper, _, _ = time_path(plan, rho, out, min(steps, 100), min(args.warmup, 10), profile=False)
-            plan.set_plane_stats(None)
-            fused_ms = fw / min(steps, 100) * 1e3
-            plain_ms = pw / min(steps, 100) * 1e3
-        info = plan.info()
-        res[prec] = dict(plan=plan, info=info, wall=wall, per=per, passes=passes, calls=calls, steps=steps,
-                         stats_ms=stats_ms, fused_ms=fused_ms, plain_ms=plain_ms, nye_ms=nye_ms,
-                         grain_law=grain_law if (prec == 32 and args.workload == "sweep-64") else None,
-                         plan_s=plan_s, graph=graph, host=host, tune=Tn.to_dict(tune) if tune is not None else None,
-                         out=out[0].double().cpu().numpy() if (B == 1 or plain_one) else None,
-                         cells=Bp * nx * ny * nz)
-        print(f"[bench] precision {prec}: {wall / steps * 1e3:.4f} ms/step, plan {plan_s:.2f} s, "
-              f"passes(ms/call) " + ", ".join(f"{k}={v / max(calls, 1):.4f}" for k, v in passes.items()),
-              file=sys.stderr, flush=True)
-        if graph:
-            print(f"[bench] precision {prec} graph replay: {graph['wall'] / steps * 1e3:.4f} ms/step",
-                  file=sys.stderr, flush=True)
-
-    r32, r64 = res[32], res[64]
-    ms32 = r32["wall"] / r32["steps"] * 1e3
-    ms64 = r64["wall"] / r64["steps"] * 1e3
-    value = r32["cells"] / (ms32 * 1e-3)
-    value64 = r64["cells"] / (ms64 * 1e-3)
-    elem = 4
-    zbytes = z_pass_bytes(r32["info"], w["n"], C, B, elem)
-    z_ms = r32["passes"]["z_fused"] / max(r32["calls"], 1)
-    achieved = zbytes / (z_ms * 1e-3) / 1e9
-    pbytes = path_bytes(r32["info"], w["n"], C, B, elem)
-    info32 = r32["info"]
-    kname = "k_z_grouped" if info32.z_groups > 1 else "k_z_serial"
-    from paper_1804_01830_amd import profiling as Pf
-    traffic = Pf.stored_traffic(os.path.join(ROOT, "profiles"), w["name"], B, kname)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else int(traffic),
-                "traffic_vs_algorithmic": None if traffic is None else round(traffic / zbytes, 3),
-                "kernel": kname, "kernel_does": "forward z FFT, 6 x C contraction with the kernel spectrum, "
-                                                "inverse z FFT (fused)",
-                "algorithmic_bytes_per_launch": int(zbytes), "avg_launch_ms": round(z_ms, 5)}
-    plan_info = {"padded": list(info32.padded), "tile_z": info32.tile_z, "ez": info32.ez,
-                 "z_groups": info32.z_groups, "mirror_y": info32.mirror_y, "mirror_z": info32.mirror_z,
-                 "xy_fused": info32.xy_fused, "yx_fused": info32.yx_fused,
-                 "rows_x": info32.rows_x, "tile_y": info32.tile_y, "ex": info32.ex, "ey": info32.ey}
+    extras = args.workload == "disk-mixed-128"
+    keep = (0,) if (B == 1 or plain_one) else ()
+    r32 = measure(w, 32, B, args, periodic, tune=not args.no_tune, graph=True, host_io=extras, stats=extras,
+                  keep_out=keep, grain_law=args.workload == "sweep-64")
+    r64 = measure(w, 64, 1 if plain_one else B, args, periodic, tune=False, keep_out=keep)
     line = {
-        "metric": METRIC, "value": round(value, 1), "unit": "cells/s", "n_gpus": 1,
-        "steps": r32["steps"], "warmup": args.warmup, "ms_per_step": round(ms32, 5),
+        "metric": METRIC, "value": round(r32["value"], 1), "unit": "cells/s", "n_gpus": 1,
+        "steps": r32["steps"], "warmup": args.warmup, "ms_per_step": round(r32["ms_per_step"], 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded)",
         "config": {"workload": w["name"], "grid": list(w["n"]), "cell": list(w["d"]), "channels": C,
                    "batch": B, "cells_per_step": cells, "precision": "fp32 transforms and contraction, "
                    "fp64 kernel coefficients and transform", "parallelism": "single GPU",
                    "boundary": "periodic in x and y, 15 replica shells" if any(periodic) else "open"},
-        "p50_ms": round(pct(r32["per"], 50), 5), "p99_ms": round(pct(r32["per"], 99), 5),
-        "fp64_plain": {"value": round(value64, 1), "ms_per_step": round(ms64, 5), "steps": r64["steps"],
-                       "batch": r64["info"].batch,
-                       "p50_ms": round(pct(r64["per"], 50), 5), "p99_ms": round(pct(r64["per"], 99), 5)},
-        "speedup_fp32_vs_fp64": round(value / value64, 3),
-        "graph_replay": {"value": round(cells / (r32["graph"]["wall"] / r32["steps"]), 1),
-                         "ms_per_step": round(r32["graph"]["wall"] / r32["steps"] * 1e3, 5),
-                         "p50_ms": round(pct(r32["graph"]["per"], 50), 5),
-                         "p99_ms": round(pct(r32["graph"]["per"], 99), 5)},
-        "tuning": r32["tune"],
-        "pass_ms": {k: round(v / max(r32["calls"], 1), 5) for k, v in r32["passes"].items()},
-        "path_algorithmic_gbs": round(pbytes / (ms32 * 1e-3) / 1e9, 1),
-        "path_frac": round(pbytes / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "b_pass_frac": round(value * b_pass_bytes(C, B, elem) / (HBM_PEAK_GBS * 1e9), 4),
-        "host_to_host": {"value": round(cells / (r32["host"]["wall"] / r32["host"]["steps"]), 1),
-                         "ms_per_step": round(r32["host"]["wall"] / r32["host"]["steps"] * 1e3, 5),
-                         "p50_ms": round(pct(r32["host"]["per"], 50) * 1e3, 5),
-                         "pcie_bytes_per_step": r32["host"]["bytes"],
-                         "note": "density from and stress to pinned host memory; not the headline value"},
-        "plan_build_s": {"fp32": round(r32["plan_s"], 3), "fp64": round(r64["plan_s"], 3)},
-        "plane_stats": {"what": "Eq. 20 mean square per plane of the FP32 stress (ddstress_plane_mean_square)",
-                        "ms": round(r32["stats_ms"], 5),
-                        "gbs": round(B * 6 * nx * ny * nz * 4 / (r32["stats_ms"] * 1e-3) / 1e9, 1),
-                        "fused_ms_per_step": round(r32["fused_ms"], 5),
-                        "plain_ms_per_step": round(r32["plain_ms"], 5),
-                        "fused_note": "stress call with the statistics in the inverse x pass (ddstress_plan_set_plane_stats), "
-                                      "and the same loop without them; both without per-pass events"},
-        "roofline": roofline,
-        "plan_info": plan_info,
     }
+    line.update(summary(r32, r64, w, C, B, periodic))
     if r32.get("grain_law") is not None:
         line["grain_law"] = r32["grain_law"]
-    if r32["nye_ms"] is not None:
+    if r32.get("nye_ms") is not None:
         line["axis_basis_channels"] = {
             "what": "rho[3l+g] = n t_l b_g from per-cell line fields (ddstress_nye_density), outside the step",
             "ms": round(r32["nye_ms"], 5),
@@ -692,7 +617,13 @@ def main():
     if base is not None:
         line["cpu_baseline"] = base
         if not any(periodic):
-            line["error_vs_oracle"] = errors_at(tg, ref, r32["out"], r64["out"])
+            line["error_vs_oracle"] = errors_at(tg, ref, r32["out"][0], r64["out"][0])
+    r32.clear()
+    r64.clear()
+    if extras and not args.no_extra_configs:
+        line["configs"] = {}
+        for name in ("poly-256", "sweep-64"):
+            line["configs"][name] = sub_config(name, args)
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -702,6 +633,194 @@ def main():
         torch.cuda.synchronize()
         line["calib_copy_bytes"] = 4 * n
     print(json.dumps(line), flush=True)
+
+
+def measure(w, prec, Bp, args, periodic, tune, graph=False, host_io=False, stats=False, keep_out=(),
+            grain_law=False):
+    """Plan (tuned in FP32), then: the headline loop (exactly args.steps steps,
+    no events inside), the latency loop (max(200, steps) single evaluations
+    with an event pair each), each pass timed alone (ddstress_plan_time_passes),
+    and on request graph replay, host-to-host steps and the plane statistics."""
+    import torch
+    from paper_1804_01830_amd import binding as Bd
+    from paper_1804_01830_amd import tuning as Tn
+    nx, ny, nz = w["n"]
+    desc = Bd.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=prec, batch=Bp, periodic=periodic)
+    t = time.perf_counter()
+    tuning = Tn.get_tuning(desc) if tune else None
+    plan = Bd.Plan(desc, tuning=tuning)
+    plan_s = time.perf_counter() - t
+    dt = torch.float32 if prec == 32 else torch.float64
+    rho, nye_ms = device_density(w, Bp, dt)
+    out = plan.new_output()
+    steps = args.steps if prec == 32 else (args.fp64_steps or args.steps)
+    # the latency loop first: the headline's steps then run on a device that
+    # has been busy for a while (its clocks settled), as in steady use
+    lat = time_latency(plan, rho, out, max(args.latency_reps, steps))
+    wall, dev_ms = time_steps(plan, rho, out, steps, args.warmup)
+    plan.set_density(rho, Bd.DEVICE_BORROW)
+    passes = plan.time_passes(out, max(20, min(steps, 100)))
+    r = dict(info=plan.info(), steps=steps, ms_per_step=wall / steps * 1e3, device_ms_per_step=dev_ms / steps,
+             lat=lat, passes=passes, plan_s=plan_s, nye_ms=nye_ms, cells=Bp * nx * ny * nz,
+             tune=Tn.to_dict(tuning) if tuning is not None else None)
+    r["value"] = r["cells"] / (r["ms_per_step"] * 1e-3)
+    if graph:
+        gw, gdev = time_steps(plan, rho, out, steps, args.warmup, graph=True)
+        r["graph"] = dict(ms=gw / steps * 1e3, dev_ms=gdev / steps,
+                          lat=time_latency(plan, rho, out, max(args.latency_reps, steps), graph=True))
+    if host_io:
+        hw, hper, hbytes = time_host_io(plan, rho, min(steps, 50), min(args.warmup, 5))
+        r["host"] = dict(wall=hw, per=hper, bytes=hbytes, steps=min(steps, 50))
+    if stats:
+        # Eq. (20) plane statistics of the stress just computed (one read of sigma)
+        stream = torch.cuda.current_stream()
+        ms_out = Bd.plane_mean_square(out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            Bd.plane_mean_square(out, ms_out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        r["stats_ms"] = e0.elapsed_time(e1) / 20
+        # the same statistics fused into the stress call (inverse x epilogue),
+        # against the same loop without them
+        k = min(steps, 100)
+        pw, _ = time_steps(plan, rho, out, k, min(args.warmup, 10))
+        plan.set_plane_stats(ms_out)
+        fw, _ = time_steps(plan, rho, out, k, min(args.warmup, 10))
+        plan.set_plane_stats(None)
+        r["fused_ms"], r["plain_ms"] = fw / k * 1e3, pw / k * 1e3
+    if grain_law:
+        r["grain_law"] = sweep_grain_law(w, plan, out)
+    if keep_out:          # the stress of these realisations, for the error against the oracle
+        plan.set_density(rho, Bd.DEVICE_BORROW)
+        plan.stress(out)
+        torch.cuda.synchronize()
+        r["out"] = {i: out[i].double().cpu().numpy() for i in keep_out}
+    plan.close()
+    del rho, out
+    torch.cuda.empty_cache()
+    print(f"[bench] {w['name']} precision {prec} B={Bp}: {r['ms_per_step']:.4f} ms/step "
+          f"(device {r['device_ms_per_step']:.4f}), p50 {pct(lat, 50):.4f} p99 {pct(lat, 99):.4f} ms, plan "
+          f"{plan_s:.2f} s, passes(ms/launch) " + ", ".join(f"{k}={v:.4f}" for k, v in passes.items()),
+          file=sys.stderr, flush=True)
+    return r
+
+
+def summary(r32, r64, w, C, B, periodic):
+    """The fields of a bench line (or sub-object) from the FP32 and FP64 runs."""
+    info = r32["info"]
+    elem = 4
+    nx, ny, nz = w["n"]
+    cells = B * nx * ny * nz
+    z_ms = r32["passes"]["z_fused"]
+    kname = "k_z_grouped" if info.z_groups > 1 else "k_z_serial"
+    zmir = z_pass_bytes(info, w["n"], C, B, elem)
+    from paper_1804_01830_amd import profiling as Pf
+    traffic = Pf.stored_traffic(os.path.join(ROOT, "profiles"), w["name"], B, kname)
+    if any(periodic):
+        # the five-pass model assumes padded x and y: the periodic plans transform Nx x Ny planes
+        zalg, basis = zmir, "algorithmic bytes of the transforms the plan runs (mirror-compressed spectrum)"
+    else:
+        zalg = survey_z_bytes(C, B, nx * ny * nz, elem)
+        basis = "five-pass model: s (4C + 24C/B + 24) per cell (full spectrum read once per launch)"
+    achieved = zalg / (z_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
+                "traffic_vs_algorithmic": None if traffic is None else round(traffic / zalg, 3),
+                "kernel": kname, "kernel_does": "forward z FFT, 6 x C contraction with the kernel spectrum, "
+                                                "inverse z FFT (fused)",
+                "algorithmic_bytes_per_launch": int(zalg), "algorithmic_basis": basis,
+                "mirror_aware_bytes_per_launch": int(zmir),
+                "mirror_aware_frac": round(zmir / (z_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "avg_launch_ms": round(z_ms, 5),
+                "avg_launch_timing": "ddstress_plan_time_passes: launches back to back between two HIP events "
+                                     "on the library's stream"}
+    ms32 = r32["ms_per_step"]
+    pbytes = path_bytes(info, w["n"], C, B, elem)
+    out = {
+        "p50_ms": round(pct(r32["lat"], 50), 5), "p99_ms": round(pct(r32["lat"], 99), 5),
+        "latency_reps": len(r32["lat"]),
+        "device_ms_per_step": round(r32["device_ms_per_step"], 5),
+        "fp64_plain": {"value": round(r64["value"], 1), "ms_per_step": round(r64["ms_per_step"], 5),
+                       "steps": r64["steps"], "batch": r64["info"].batch,
+                       "p50_ms": round(pct(r64["lat"], 50), 5), "p99_ms": round(pct(r64["lat"], 99), 5),
+                       "pass_ms": {k: round(v, 5) for k, v in r64["passes"].items()}},
+        "speedup_fp32_vs_fp64": round(r32["value"] / r64["value"], 3),
+        "tuning": r32["tune"],
+        "pass_ms": {k: round(v, 5) for k, v in r32["passes"].items()},
+        "path_algorithmic_gbs": round(pbytes / (ms32 * 1e-3) / 1e9, 1),
+        "path_frac": round(pbytes / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "plan_build_s": {"fp32": round(r32["plan_s"], 3), "fp64": round(r64["plan_s"], 3)},
+        "roofline": roofline,
+        "plan_info": {"padded": list(info.padded), "tile_z": info.tile_z, "ez": info.ez,
+                      "z_groups": info.z_groups, "mirror_y": info.mirror_y, "mirror_z": info.mirror_z,
+                      "xy_fused": info.xy_fused, "yx_fused": info.yx_fused,
+                      "rows_x": info.rows_x, "tile_y": info.tile_y, "ex": info.ex, "ey": info.ey},
+    }
+    if not any(periodic):
+        out["b_pass_frac"] = round(r32["value"] * b_pass_bytes(C, B, elem) / (HBM_PEAK_GBS * 1e9), 4)
+    if "graph" in r32:
+        g = r32["graph"]
+        out["graph_replay"] = {"value": round(cells / (g["ms"] * 1e-3), 1), "ms_per_step": round(g["ms"], 5),
+                               "p50_ms": round(pct(g["lat"], 50), 5), "p99_ms": round(pct(g["lat"], 99), 5)}
+    if "host" in r32:
+        h = r32["host"]
+        out["host_to_host"] = {"value": round(cells / (h["wall"] / h["steps"]), 1),
+                               "ms_per_step": round(h["wall"] / h["steps"] * 1e3, 5),
+                               "p50_ms": round(pct(h["per"], 50) * 1e3, 5),
+                               "pcie_bytes_per_step": h["bytes"],
+                               "note": "density from and stress to pinned host memory; not the headline value"}
+    if "stats_ms" in r32:
+        out["plane_stats"] = {"what": "Eq. 20 mean square per plane of the FP32 stress (ddstress_plane_mean_square)",
+                              "ms": round(r32["stats_ms"], 5),
+                              "gbs": round(B * 6 * nx * ny * nz * 4 / (r32["stats_ms"] * 1e-3) / 1e9, 1),
+                              "fused_ms_per_step": round(r32["fused_ms"], 5),
+                              "plain_ms_per_step": round(r32["plain_ms"], 5),
+                              "fused_note": "stress call with the statistics in the inverse x pass "
+                                            "(ddstress_plan_set_plane_stats), and the same loop without them"}
+    return out
+
+
+GOLDEN = {"poly-256": ("poly_layer_256x256x64",), "sweep-64": ("poly_sweep_128x128x32_b0", "poly_sweep_128x128x32_b63")}
+
+
+def sub_config(name, args):
+    """One more workload timed like the headline (FP32 batched and tuned, FP64
+    plain with one realisation), with its error on the stored oracle values of
+    tests/golden (written by the oracle alone)."""
+    import numpy as np
+    w = make_workload(name)
+    B, C = w["rho"].shape[0], w["rho"].shape[1]
+    nx, ny, nz = w["n"]
+    print(f"[bench] sub-config {w['name']} B={B} C={C}", file=sys.stderr, flush=True)
+    goldens = []
+    for gname in GOLDEN[name]:
+        with open(os.path.join(ROOT, "tests", "golden", gname + ".json")) as f:
+            goldens.append(json.load(f))
+    r32 = measure(w, 32, B, args, (False, False), tune=not args.no_tune,
+                  keep_out=tuple(g["batch_index"] for g in goldens))
+    r64 = measure(w, 64, 1, args, (False, False), tune=False, keep_out=(0,))
+    sub = {"workload": w["name"], "value": round(r32["value"], 1), "unit": "cells/s",
+           "ms_per_step": round(r32["ms_per_step"], 5), "steps": r32["steps"], "batch": B, "channels": C,
+           "grid": list(w["n"]), "cells_per_step": B * nx * ny * nz}
+    sub.update(summary(r32, r64, w, C, B, (False, False)))
+    errs = {}
+    for gname, g in zip(GOLDEN[name], goldens):
+        tg = np.array(g["targets"])
+        ref = np.array(g["sigma_voigt"]).T
+        bi = g["batch_index"]
+        e32, w32 = rel_l2_targets(r32["out"][bi][:, tg[:, 2], tg[:, 1], tg[:, 0]], ref)
+        rec = {"realisation": bi, "targets": len(tg), "fp32_rel_l2_per_component": [float("%.3e" % x) for x in e32],
+               "fp32_rel_l2": float("%.3e" % w32)}
+        if bi == 0:
+            e64, w64 = rel_l2_targets(r64["out"][0][:, tg[:, 2], tg[:, 1], tg[:, 0]], ref)
+            rec.update({"fp64_rel_l2_per_component": [float("%.3e" % x) for x in e64], "fp64_rel_l2": float("%.3e" % w64)})
+        errs[gname] = rec
+    sub["error_vs_oracle"] = {"oracle": "stored FP64 direct-sum values (tests/golden, written by the oracle only)",
+                              "fixtures": errs}
+    return sub
 
 
 if __name__ == "__main__":

@@ -280,6 +280,19 @@ ddstress_status ddstress_plan_set_graph(ddstress_plan plan, int32_t enable);
  * the recorded events; call it after the stream work has been issued. */
 ddstress_status ddstress_plan_get_pass_times(ddstress_plan plan, double ms[5], int64_t* calls);
 
+/* Average device milliseconds per launch of each of the five passes (order
+ * as for ddstress_plan_get_pass_times): every pass is enqueued `reps` >= 1
+ * times back to back on `stream`, in path order, on the current densities,
+ * between two HIP events per pass (two events per pass, not per launch, so
+ * the per-launch event cost does not enter). A pass reads only what the one
+ * before it wrote, so repeating it recomputes the same output and `sigma`
+ * (device buffer [B][6][Nz][Ny][Nx], plan precision) ends with the stress of
+ * one ordinary evaluation. A pass fused into the previous one reports zero.
+ * Synchronises `stream`. DDSTRESS_E_STATE if no density was set. Measurement
+ * only: the same kernels and launch shapes as ddstress_stress. */
+ddstress_status ddstress_plan_time_passes(ddstress_plan plan, void* sigma, int32_t reps, double ms[5],
+                                          void* stream);
+
 /* Free a plan and its device memory (synchronises the device first). NULL is
  * accepted. */
 ddstress_status ddstress_plan_destroy(ddstress_plan plan);

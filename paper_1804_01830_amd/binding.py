@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STAT
 # names exported by the library, in header order
 EXPORTS = ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
            "ddstress_set_density", "ddstress_stress",
-           "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times",
+           "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times", "ddstress_plan_time_passes",
            "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_plan_set_plane_stats", "ddstress_nye_density",
            "ddstress_plane_mean_square",
            "ddstress_relax_create", "ddstress_relax_set_load", "ddstress_relax_iterate", "ddstress_relax_update_norm",
@@ -97,6 +97,7 @@ def load(path=LIB_PATH):
     lib.ddstress_plan_share.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
     lib.ddstress_stress_batch.argtypes = [P, P, P, ctypes.c_int32, P]
     lib.ddstress_plan_get_pass_times.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.ddstress_plan_time_passes.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), P]
     lib.ddstress_plan_set_plane_stats.argtypes = [P, P]
     lib.ddstress_plan_set_plane_stats.restype = ctypes.c_int
     lib.ddstress_nye_density.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
@@ -120,7 +121,7 @@ def load(path=LIB_PATH):
     for name in ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
                  "ddstress_set_density", "ddstress_stress",
                  "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_graph", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times",
-                 "ddstress_plan_destroy", "ddstress_kernel_realspace"):
+                 "ddstress_plan_time_passes", "ddstress_plan_destroy", "ddstress_kernel_realspace"):
         getattr(lib, name).restype = ctypes.c_int
     lib.ddstress_last_error.restype = ctypes.c_char_p
     lib.ddstress_last_error.argtypes = []
@@ -277,6 +278,17 @@ class Plan:
         calls = ctypes.c_int64()
         check(load().ddstress_plan_get_pass_times(self._h, ms, ctypes.byref(calls)))
         return dict(zip(PASS_NAMES, list(ms))), calls.value
+
+    def time_passes(self, sigma, reps, stream=None):
+        """Average device ms per launch of each pass (dict pass name -> ms),
+        each pass enqueued `reps` times back to back between two events on
+        the current densities; `sigma` (CUDA tensor of the output shape)
+        receives the stress."""
+        self._check_tensor(sigma, (self.batch, 6))
+        ms = (ctypes.c_double * 5)()
+        check(load().ddstress_plan_time_passes(self._h, ctypes.c_void_p(sigma.data_ptr()), int(reps), ms,
+                                               _stream_handle(stream)))
+        return dict(zip(PASS_NAMES, list(ms)))
 
     def close(self):
         if self._h:

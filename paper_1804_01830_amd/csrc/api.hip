@@ -364,8 +364,13 @@ void upload_twiddles(ddstress_plan_s* p, hipStream_t st) {
     check_hip(hipStreamSynchronize(st), "twiddle upload");
 }
 
+// Pass k (0..4: x forward, y forward, fused z, y inverse, x inverse) of one
+// evaluation of the first nb densities. Where the plan fuses forward x and y
+// (inverse y and x), pass 0 (3) runs both and pass 1 (4) enqueues nothing.
+// Each pass reads only what the previous one wrote, so a pass enqueued
+// several times in a row recomputes the same output.
 template <typename T>
-void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t st) {
+void enqueue_pass(ddstress_plan_s* p, int k, const T* rho, T* sigma, int nb, hipStream_t st) {
     Shape s = p->shape;
     s.B = nb;       // realisations evaluated by this call (<= the plan's batch)
     cplx<T>* w1 = p->work1.as<cplx<T>>();
@@ -374,20 +379,19 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
     const int64_t BC = (int64_t)s.B * s.C;
     const int64_t B6 = (int64_t)s.B * 6;
     const int Nx = s.N[0], Ny = s.N[1], Nz = s.N[2], Py = s.P[1];
-    p->mark(st);
-    // x forward: rows (b, c, z, y) of Nx reals -> M+1 complex
-    bool fused_fwd = false;
-    if constexpr (sizeof(T) == 4) {
-        if (p->xy) {        // one kernel; the y pass's time shows as zero
-            launch_xy_fwd(rho, w2, BC * Nz, Py, s.M, Ny, Nx, s.wx, tw, st);
-            p->mark(st);
-            p->mark_fused();
-            fused_fwd = true;
+    const bool xy = sizeof(T) == 4 && p->xy;
+    const bool yx = sizeof(T) == 4 && p->yx;
+    if (k == 0) {
+        if constexpr (sizeof(T) == 4) {
+            if (xy) {
+                launch_xy_fwd(rho, w2, BC * Nz, Py, s.M, Ny, Nx, s.wx, tw, st);
+                return;
+            }
         }
-    }
-    if (!fused_fwd) {
+        // x forward: rows (b, c, z, y) of Nx reals -> M+1 complex
         launch_x_r2c<T>(s.M, p->ex, rho, w1, BC * Nz * Ny, Nx, Nx, s.wx, tw, p->rows_x, st);
-        p->mark(st);
+    } else if (k == 1) {
+        if (xy) return;
         // y forward: Ny rows -> Py rows
         ColGeom gy{};
         gy.ncols = s.M1;
@@ -400,57 +404,73 @@ void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t 
         gy.ors = s.wx;
         gy.ops = (int64_t)Py * s.wx;
         launch_col_fft<T>(Py, p->ey, true, w1, w2, gy, tw, p->tk_y, st);
-        p->mark(st);
-    }
-    // z forward + contraction + z inverse
-    ZGeom gz{};
-    gz.nky_s = s.nkys;
-    gz.nkz_s = s.nkzs;
-    gz.sgn_y = s.sgn_y;
-    gz.sgn_z = s.sgn_z;
-    gz.ncols = s.M1;
-    gz.ntiles = s.ntz;
-    gz.nky = Py;
-    gz.nz = Nz;
-    gz.C = s.C;
-    gz.B = s.B;
-    gz.irs = (int64_t)Py * s.wx;
-    gz.iqs = (int64_t)Nz * Py * s.wx;
-    gz.ios = s.wx;
-    gz.ors = gz.irs;
-    gz.oqs = gz.iqs;
-    gz.oos = gz.ios;
-    launch_z_fused<T>(s.P[2], p->ez, s.zg, w2, w1, p->spec->as<T>(), gz, tw, s.tkz, st);
-    p->mark(st);
-    // y inverse: Py rows -> Ny rows
-    ColGeom gi{};
-    gi.ncols = s.M1;
-    gi.n_in = Py;
-    gi.n_out = Ny;
-    gi.nouter = 1;
-    gi.nplanes = B6 * Nz;
-    gi.irs = s.wx;
-    gi.ips = (int64_t)Py * s.wx;
-    gi.ors = s.wx;
-    gi.ops = (int64_t)Ny * s.wx;
-    // plane statistics (Eq. 20) from per-row sums of the inverse x pass
-    double* rowsq = p->plane_stats ? p->rowsq.as<double>() : nullptr;
-    const double inv_plane = 1.0 / ((double)Nx * (double)Ny);
-    if constexpr (sizeof(T) == 4) {
-        if (p->yx) {        // one kernel; the x pass's time shows as zero
-            launch_yx_inv(w1, sigma, B6 * Nz, Py, s.M, Ny, Nx, s.wx, tw, st, rowsq);
+    } else if (k == 2) {
+        // z forward + contraction + z inverse
+        ZGeom gz{};
+        gz.nky_s = s.nkys;
+        gz.nkz_s = s.nkzs;
+        gz.sgn_y = s.sgn_y;
+        gz.sgn_z = s.sgn_z;
+        gz.ncols = s.M1;
+        gz.ntiles = s.ntz;
+        gz.nky = Py;
+        gz.nz = Nz;
+        gz.C = s.C;
+        gz.B = s.B;
+        gz.irs = (int64_t)Py * s.wx;
+        gz.iqs = (int64_t)Nz * Py * s.wx;
+        gz.ios = s.wx;
+        gz.ors = gz.irs;
+        gz.oqs = gz.iqs;
+        gz.oos = gz.ios;
+        launch_z_fused<T>(s.P[2], p->ez, s.zg, w2, w1, p->spec->as<T>(), gz, tw, s.tkz, st);
+    } else if (k == 3 || k == 4) {
+        // plane statistics (Eq. 20) from per-row sums of the inverse x pass
+        double* rowsq = p->plane_stats ? p->rowsq.as<double>() : nullptr;
+        const double inv_plane = 1.0 / ((double)Nx * (double)Ny);
+        if (k == 3) {
+            if constexpr (sizeof(T) == 4) {
+                if (yx) {
+                    launch_yx_inv(w1, sigma, B6 * Nz, Py, s.M, Ny, Nx, s.wx, tw, st, rowsq);
+                    if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, p->plane_stats, st);
+                    return;
+                }
+            }
+            // y inverse: Py rows -> Ny rows
+            ColGeom gi{};
+            gi.ncols = s.M1;
+            gi.n_in = Py;
+            gi.n_out = Ny;
+            gi.nouter = 1;
+            gi.nplanes = B6 * Nz;
+            gi.irs = s.wx;
+            gi.ips = (int64_t)Py * s.wx;
+            gi.ors = s.wx;
+            gi.ops = (int64_t)Ny * s.wx;
+            launch_col_fft<T>(Py, p->ey, false, w1, w2, gi, tw, p->tk_y, st);
+        } else {
+            if (yx) return;
+            // x inverse: rows (b, v, z, y) -> Nx reals
+            launch_x_c2r<T>(s.M, p->ex, w2, sigma, B6 * Nz * Ny, Nx, s.wx, Nx, tw, p->rows_x, st, rowsq);
             if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, p->plane_stats, st);
-            p->mark(st);
-            p->mark_fused();
-            return;
         }
     }
-    launch_col_fft<T>(Py, p->ey, false, w1, w2, gi, tw, p->tk_y, st);
+}
+
+// Whether pass k runs inside the previous pass's kernel (and enqueues nothing).
+bool pass_fused_away(const ddstress_plan_s* p, int k) {
+    if (p->shape.elem != 4) return false;
+    return (k == 1 && p->xy) || (k == 4 && p->yx);
+}
+
+template <typename T>
+void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t st) {
     p->mark(st);
-    // x inverse: rows (b, v, z, y) -> Nx reals
-    launch_x_c2r<T>(s.M, p->ex, w2, sigma, B6 * Nz * Ny, Nx, s.wx, Nx, tw, p->rows_x, st, rowsq);
-    if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, p->plane_stats, st);
-    p->mark(st);
+    for (int k = 0; k < 5; ++k) {
+        enqueue_pass<T>(p, k, rho, sigma, nb, st);
+        if (pass_fused_away(p, k)) p->mark_fused();     // no event: its time shows as zero
+        else p->mark(st);
+    }
 }
 
 template <typename T>
@@ -935,6 +955,44 @@ ddstress_status ddstress_plan_get_pass_times(ddstress_plan plan, double ms[5], i
         plan->fold_events();
         for (int k = 0; k < 5; ++k) ms[k] = plan->pass_ms[k];
         if (calls) *calls = plan->timed_calls;
+    });
+}
+
+ddstress_status ddstress_plan_time_passes(ddstress_plan plan, void* sigma, int32_t reps, double ms[5],
+                                          void* stream) {
+    return guarded([&] {
+        if (!plan || !sigma || !ms) fail(DDSTRESS_E_INVALID, "NULL argument");
+        if (reps < 1) fail(DDSTRESS_E_INVALID, "reps must be >= 1");
+        if (!plan->have_density) fail(DDSTRESS_E_STATE, "no density set on this plan");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        hipEvent_t ev[10] = {};
+        try {
+            for (auto& e : ev) check_hip(hipEventCreate(&e), "event create");
+            for (int k = 0; k < 5; ++k) {
+                check_hip(hipEventRecord(ev[2 * k], st), "event record");
+                if (!pass_fused_away(plan, k))
+                    for (int r = 0; r < reps; ++r) {
+                        if (plan->shape.elem == 4)
+                            enqueue_pass<float>(plan, k, static_cast<const float*>(plan->rho),
+                                                static_cast<float*>(sigma), plan->shape.B, st);
+                        else
+                            enqueue_pass<double>(plan, k, static_cast<const double*>(plan->rho),
+                                                 static_cast<double*>(sigma), plan->shape.B, st);
+                    }
+                check_hip(hipEventRecord(ev[2 * k + 1], st), "event record");
+            }
+            check_hip(hipEventSynchronize(ev[9]), "event sync");
+            for (int k = 0; k < 5; ++k) {
+                float t = 0.f;
+                check_hip(hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]), "event time");
+                ms[k] = pass_fused_away(plan, k) ? 0.0 : (double)t / reps;
+            }
+        } catch (...) {
+            for (auto& e : ev)
+                if (e) (void)hipEventDestroy(e);
+            throw;
+        }
+        for (auto& e : ev) (void)hipEventDestroy(e);
     });
 }
 

@@ -105,3 +105,31 @@ def test_host_buffers_give_device_bits(precision):
     with pytest.raises(ValueError):
         plan.stress(out_h)                    # a CPU tensor needs where=HOST
     plan.close()
+
+
+@pytest.mark.parametrize("n,precision", [((20, 12, 6), 64), ((72, 70, 5), 32), ((128, 128, 32), 32)])
+def test_timed_passes_give_the_stress_of_one_call(n, precision):
+    """ddstress_plan_time_passes enqueues every pass several times in a row
+    (each reads only what the previous pass wrote): the stress it leaves is
+    bit for bit that of one ordinary call, and every pass that runs reports a
+    positive average (a pass fused into the previous one reports zero)."""
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w = W.random_field(n, n_lines=1, batch=2, seed=5, d=(1.0, 1.0, 2.0))
+    dt = torch.float32 if precision == 32 else torch.float64
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=precision, batch=2)
+    plan = B.Plan(desc)
+    info = plan.info()
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=dt).contiguous()
+    plan.set_density(rho)
+    ref = plan.new_output()
+    plan.stress(ref)
+    out = plan.new_output()
+    out.fill_(float("nan"))
+    ms = plan.time_passes(out, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    fused = {"y_fwd": bool(info.xy_fused), "x_c2r": bool(info.yx_fused)}
+    for k, v in ms.items():
+        assert (v == 0.0) if fused.get(k, False) else (v > 0.0), (k, v, ms)
+    plan.close()
