@@ -320,6 +320,26 @@ ddstress_status ddstress_kernel_realspace(const ddstress_desc* desc, int32_t lin
  * switches the statistics off. Drops the plan's captured graphs. */
 ddstress_status ddstress_plan_set_plane_stats(ddstress_plan plan, double* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ddstress_stress_batch with the plane statistics of
+ * ddstress_plan_set_plane_stats, allocating nothing. Evaluates the first
+ * `nbatch` densities `rho` [nbatch][C][Nz][Ny][Nx] into `sigma`
+ * [nbatch][6][Nz][Ny][Nx] (device buffers, plan precision) and writes
+ * stats[b][v][k] (device, nbatch * 6 * Nz doubles), with the same kernels,
+ * arithmetic and bits as ddstress_stress_batch on a plan whose statistics
+ * are set. The per-row sums behind the statistics go to a static device array
+ * of 2^21 doubles (16 MiB) that each GPU the library runs on holds until the
+ * process ends, instead of a plan-owned buffer: nbatch * 6 * Nz * Ny above
+ * 2^21 is DDSTRESS_E_UNSUPPORTED. Every row sum is written before it is read,
+ * so nothing needs clearing between calls; calls that overlap on one GPU
+ * (concurrent streams, plans or threads) share that array and race. Launches
+ * directly (no graph replay, no profiling events) and ignores the plan's own
+ * statistics setting; calls no hipMalloc, hipFree or allocating routine.
+ * Enqueued on `stream`. */
+ddstress_status ddstress_stress_batch_stats_noalloc(ddstress_plan plan, const void* rho, void* sigma, int32_t nbatch,
+                                                   double* stats, void* stream);
+
 /* Density channels in the axis basis (the Nye tensor) for line directions
  * that vary from cell to cell. Sec. 2.1 takes the stress of a volume element
  * as linear in the line direction t; that is exact for infinitesimal

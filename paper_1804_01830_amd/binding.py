@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_STAT
 EXPORTS = ("ddstress_plan_footprint", "ddstress_autotune", "ddstress_plan_create", "ddstress_plan_create_tuned",
            "ddstress_set_density", "ddstress_stress",
            "ddstress_plan_share", "ddstress_stress_batch", "ddstress_plan_get_info", "ddstress_plan_set_profiling", "ddstress_plan_set_graph", "ddstress_plan_get_pass_times", "ddstress_plan_time_passes",
-           "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_plan_set_plane_stats", "ddstress_nye_density",
+           "ddstress_plan_destroy", "ddstress_kernel_realspace", "ddstress_plan_set_plane_stats", "ddstress_stress_batch_stats_noalloc",
+           "ddstress_nye_density",
            "ddstress_plane_mean_square",
            "ddstress_relax_create", "ddstress_relax_set_load", "ddstress_relax_iterate", "ddstress_relax_update_norm",
            "ddstress_relax_solve", "ddstress_relax_stress", "ddstress_relax_displacement", "ddstress_relax_get_info", "ddstress_relax_destroy",
@@ -100,6 +101,8 @@ def load(path=LIB_PATH):
     lib.ddstress_plan_time_passes.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), P]
     lib.ddstress_plan_set_plane_stats.argtypes = [P, P]
     lib.ddstress_plan_set_plane_stats.restype = ctypes.c_int
+    lib.ddstress_stress_batch_stats_noalloc.argtypes = [P, P, P, ctypes.c_int32, P, P]
+    lib.ddstress_stress_batch_stats_noalloc.restype = ctypes.c_int
     lib.ddstress_nye_density.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
                                          ctypes.c_int32, P, P]
     lib.ddstress_nye_density.restype = ctypes.c_int
@@ -278,6 +281,21 @@ class Plan:
         calls = ctypes.c_int64()
         check(load().ddstress_plan_get_pass_times(self._h, ms, ctypes.byref(calls)))
         return dict(zip(PASS_NAMES, list(ms))), calls.value
+
+    def stress_batch_stats_noalloc(self, rho, sigma, nbatch, stats, stream=None):
+        """As stress_batch, also writing the Eq. (20) plane statistics of the
+        result to ``stats`` (CUDA float64 (nbatch, 6, Nz)); the library
+        allocates nothing for it (its row sums live in a static device array)."""
+        import torch
+        self._check_tensor(rho, (nbatch, self.channels))
+        self._check_tensor(sigma, (nbatch, 6))
+        if (not stats.is_cuda or stats.dtype != torch.float64 or not stats.is_contiguous()
+                or tuple(stats.shape) != (nbatch, 6, self.n[2])):
+            raise ValueError(f"expected a contiguous CUDA float64 tensor of shape {(nbatch, 6, self.n[2])}")
+        check(load().ddstress_stress_batch_stats_noalloc(self._h, ctypes.c_void_p(rho.data_ptr()),
+                                                         ctypes.c_void_p(sigma.data_ptr()), int(nbatch),
+                                                         ctypes.c_void_p(stats.data_ptr()), _stream_handle(stream)))
+        return sigma
 
     def time_passes(self, sigma, reps, stream=None):
         """Average device ms per launch of each pass (dict pass name -> ms),

@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -369,8 +370,17 @@ void upload_twiddles(ddstress_plan_s* p, hipStream_t st) {
 // (inverse y and x), pass 0 (3) runs both and pass 1 (4) enqueues nothing.
 // Each pass reads only what the previous one wrote, so a pass enqueued
 // several times in a row recomputes the same output.
+// Plane statistics targets of one call: per-row sums of squares and the
+// per-plane results (both NULL: no statistics).
+struct StatsTarget {
+    double* rowsq;
+    double* stats;
+};
+StatsTarget plan_stats(const ddstress_plan_s* p);
+
 template <typename T>
-void enqueue_pass(ddstress_plan_s* p, int k, const T* rho, T* sigma, int nb, hipStream_t st) {
+void enqueue_pass(ddstress_plan_s* p, int k, const T* rho, T* sigma, int nb, hipStream_t st,
+                  StatsTarget stt) {
     Shape s = p->shape;
     s.B = nb;       // realisations evaluated by this call (<= the plan's batch)
     cplx<T>* w1 = p->work1.as<cplx<T>>();
@@ -426,13 +436,14 @@ void enqueue_pass(ddstress_plan_s* p, int k, const T* rho, T* sigma, int nb, hip
         launch_z_fused<T>(s.P[2], p->ez, s.zg, w2, w1, p->spec->as<T>(), gz, tw, s.tkz, st);
     } else if (k == 3 || k == 4) {
         // plane statistics (Eq. 20) from per-row sums of the inverse x pass
-        double* rowsq = p->plane_stats ? p->rowsq.as<double>() : nullptr;
+        double* rowsq = stt.stats ? stt.rowsq : nullptr;
+        double* stats_out = stt.stats;
         const double inv_plane = 1.0 / ((double)Nx * (double)Ny);
         if (k == 3) {
             if constexpr (sizeof(T) == 4) {
                 if (yx) {
                     launch_yx_inv(w1, sigma, B6 * Nz, Py, s.M, Ny, Nx, s.wx, tw, st, rowsq);
-                    if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, p->plane_stats, st);
+                    if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, stats_out, st);
                     return;
                 }
             }
@@ -452,9 +463,13 @@ void enqueue_pass(ddstress_plan_s* p, int k, const T* rho, T* sigma, int nb, hip
             if (yx) return;
             // x inverse: rows (b, v, z, y) -> Nx reals
             launch_x_c2r<T>(s.M, p->ex, w2, sigma, B6 * Nz * Ny, Nx, s.wx, Nx, tw, p->rows_x, st, rowsq);
-            if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, p->plane_stats, st);
+            if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, stats_out, st);
         }
     }
+}
+
+StatsTarget plan_stats(const ddstress_plan_s* p) {
+    return {p->plane_stats ? p->rowsq.as<double>() : nullptr, p->plane_stats};
 }
 
 // Whether pass k runs inside the previous pass's kernel (and enqueues nothing).
@@ -467,10 +482,36 @@ template <typename T>
 void run_stress(ddstress_plan_s* p, const T* rho, T* sigma, int nb, hipStream_t st) {
     p->mark(st);
     for (int k = 0; k < 5; ++k) {
-        enqueue_pass<T>(p, k, rho, sigma, nb, st);
+        enqueue_pass<T>(p, k, rho, sigma, nb, st, plan_stats(p));
         if (pass_fused_away(p, k)) p->mark_fused();     // no event: its time shows as zero
         else p->mark(st);
     }
+}
+
+// Row sums of squares for ddstress_stress_batch_stats_noalloc: a file-scope
+// device array (each GPU the library runs on holds its own copy until the
+// process ends), addressed from the host through the per-device address that
+// hipGetSymbolAddress returns, never through the array's host-side name.
+constexpr size_t kNoAllocRowsq = size_t(1) << 21;      // doubles (16 MiB)
+static __device__ __align__(256) double scratch[kNoAllocRowsq];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of the scratch array (looked up once per device).
+double* device_scratch() {
+    int dev = -1;
+    check_hip(hipGetDevice(&dev), "current device");
+    if (dev < 0 || dev >= kMaxDevices) fail(DDSTRESS_E_UNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "scratch symbol address");
+        if (!ptr) fail(DDSTRESS_E_DEVICE, "scratch symbol address is NULL");
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[dev];
 }
 
 template <typename T>
@@ -899,6 +940,31 @@ ddstress_status ddstress_stress_batch(ddstress_plan plan, const void* rho, void*
     });
 }
 
+ddstress_status ddstress_stress_batch_stats_noalloc(ddstress_plan plan, const void* rho, void* sigma, int32_t nbatch,
+                                                   double* stats, void* stream) {
+    return guarded([&] {
+        if (!plan) fail(DDSTRESS_E_INVALID, "plan is NULL");
+        if (!rho || !sigma || !stats) fail(DDSTRESS_E_INVALID, "NULL buffer");
+        if (nbatch < 1 || nbatch > plan->shape.B) fail(DDSTRESS_E_INVALID, "nbatch must lie in [1, batch]");
+        const Shape& s = plan->shape;
+        const size_t rows = (size_t)nbatch * 6 * s.N[2] * (size_t)s.N[1];
+        if (rows > kNoAllocRowsq)
+            fail(DDSTRESS_E_UNSUPPORTED, "nbatch * 6 * Nz * Ny = " + std::to_string(rows) +
+                                             " row sums exceed the static scratch of " +
+                                             std::to_string(kNoAllocRowsq) + " doubles");
+        const StatsTarget stt{device_scratch(), stats};
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        for (int k = 0; k < 5; ++k) {
+            if (s.elem == 4)
+                enqueue_pass<float>(plan, k, static_cast<const float*>(rho), static_cast<float*>(sigma), nbatch, st,
+                                    stt);
+            else
+                enqueue_pass<double>(plan, k, static_cast<const double*>(rho), static_cast<double*>(sigma), nbatch,
+                                     st, stt);
+        }
+    });
+}
+
 ddstress_status ddstress_plan_get_info(ddstress_plan plan, ddstress_info* info) {
     return guarded([&] {
         if (!plan || !info) fail(DDSTRESS_E_INVALID, "NULL argument");
@@ -974,10 +1040,10 @@ ddstress_status ddstress_plan_time_passes(ddstress_plan plan, void* sigma, int32
                     for (int r = 0; r < reps; ++r) {
                         if (plan->shape.elem == 4)
                             enqueue_pass<float>(plan, k, static_cast<const float*>(plan->rho),
-                                                static_cast<float*>(sigma), plan->shape.B, st);
+                                                static_cast<float*>(sigma), plan->shape.B, st, plan_stats(plan));
                         else
                             enqueue_pass<double>(plan, k, static_cast<const double*>(plan->rho),
-                                                 static_cast<double*>(sigma), plan->shape.B, st);
+                                                 static_cast<double*>(sigma), plan->shape.B, st, plan_stats(plan));
                     }
                 check_hip(hipEventRecord(ev[2 * k + 1], st), "event record");
             }
