@@ -95,3 +95,33 @@ def test_poisson_replay_is_deterministic():
         _run(srv, clock, reqs)
         outs.append([(r.rid, r.start, r.done) for r in reqs])
     assert outs[0] == outs[1]
+
+
+def test_results_count_against_the_budget_until_released():
+    """Each launched batch reserves its results' bytes; released results
+    return them. With a budget that holds one batch of results, the second
+    batch waits for the first batch's release."""
+    ex, clock = _sim({A: (GB, GB)}, lat=lambda k, nb: 1.0)
+    ex.result_sizes[A] = GB // 2
+    srv = Server(ex, hbm_budget=3 * GB, max_batch=2, max_slots_per_shape=1)
+    reqs = [Request(i, A, rho=i, arrival=0.0) for i in range(4)]
+    released_at = []
+
+    def consume(server, r):
+        assert server.used <= server.budget
+        released_at.append(clock())
+        server.release(r)
+
+    st = srv.run(reqs, clock, sleep=clock.advance, on_complete=consume)
+    assert st["requests"] == 4 and st["results_held_bytes"] == 0
+    assert st["hbm_peak_bytes"] == 3 * GB                 # spectrum + slot + one batch of results
+    assert [r.start for r in reqs] == [0.0, 0.0, 1.0, 1.0]
+
+
+def test_unreleased_results_that_block_admission_raise():
+    ex, clock = _sim({A: (GB, GB)}, lat=lambda k, nb: 1.0)
+    ex.result_sizes[A] = GB
+    srv = Server(ex, hbm_budget=3 * GB, max_batch=1, max_slots_per_shape=1)
+    reqs = [Request(i, A, rho=i, arrival=0.0) for i in range(2)]
+    with pytest.raises(RuntimeError, match="unreleased results"):
+        _run(srv, clock, reqs)
