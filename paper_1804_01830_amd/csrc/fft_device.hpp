@@ -209,12 +209,28 @@ struct RowPad {        // element i of row r at r*ld + i + (i >> s): one pad ele
     __device__ __forceinline__ int operator()(int i, int r) const { return r * ld + i + (i >> s); }
 };
 
+// Synchronisation between the stages of a transform. A transform whose
+// threads (and LDS region) all belong to one wave needs no workgroup barrier:
+// the LDS executes one wave's instructions in order, so its writes are seen by
+// its later reads; only the compiler must keep them in order (WAVE). Other
+// transforms take a workgroup barrier.
+template <bool WAVE>
+__device__ __forceinline__ void stage_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // One radix-R Stockham stage. Butterfly b = j + Tc*q (q < E/R) reads
 // x[b + r N/R], multiplies by exp(-/+ 2 pi i (b mod Ns) r / (Ns R)), applies
 // the length-R DFT and writes (b / Ns) Ns R + (b mod Ns) + r Ns.
 // HZ: elements N/2 .. N-1 of the input are zero (zero padding); the first
 // stage then never reads them (same values).
-template <typename T, int N, int E, bool FWD, int Ns, int R, bool HZ, class Lay>
+template <typename T, int N, int E, bool FWD, int Ns, int R, bool HZ, bool WAVE, class Lay>
 __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
                                           const cplx<T>* __restrict__ tw, bool act) {
     constexpr int Tc = N / E;
@@ -228,7 +244,7 @@ __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay l
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = reg[q + r * NB];
     } else {
-        __syncthreads();
+        stage_sync<WAVE>();
         if (act) {
 #pragma unroll
             for (int q = 0; q < NB; ++q)
@@ -254,7 +270,7 @@ __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay l
 #pragma unroll
             for (int r = 0; r < R; ++r) reg[q + r * NB] = v[q][r];
     } else {
-        __syncthreads();   // every thread has read its inputs (or the buffer's previous user is done)
+        stage_sync<WAVE>();   // every thread has read its inputs (or the buffer's previous user is done)
         if (act) {
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
@@ -267,13 +283,13 @@ __device__ __forceinline__ void fft_stage(cplx<T> (&reg)[E], cplx<T>* lds, Lay l
     }
 }
 
-template <typename T, int N, int E, bool FWD, int Ns, bool HZ, class Lay>
+template <typename T, int N, int E, bool FWD, int Ns, bool HZ, bool WAVE, class Lay>
 __device__ __forceinline__ void fft_stages(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
                                            const cplx<T>* __restrict__ tw, bool act) {
     if constexpr (Ns < N) {
         constexpr int R = cmin(cmin(8, E), N / Ns);
-        fft_stage<T, N, E, FWD, Ns, R, HZ>(reg, lds, lay, c, j, tw, act);
-        fft_stages<T, N, E, FWD, Ns * R, HZ>(reg, lds, lay, c, j, tw, act);
+        fft_stage<T, N, E, FWD, Ns, R, HZ, WAVE>(reg, lds, lay, c, j, tw, act);
+        fft_stages<T, N, E, FWD, Ns * R, HZ, WAVE>(reg, lds, lay, c, j, tw, act);
     }
 }
 
@@ -313,7 +329,7 @@ __device__ __forceinline__ void load_tw_stages(cplx<T> (&w)[TWC], int j, const c
 // regions lds + k * region. HZ: inputs m >= E/2 of every transform are zero
 // (zero-padded data) and are not read. Threads with act == false (whole
 // waves) take part in the barriers without touching LDS or computing.
-template <typename T, int N, int E, bool FWD, bool HZ, int Ns, int R, int KT, int K, int TWC, class Lay>
+template <typename T, int N, int E, bool FWD, bool HZ, int Ns, int R, int KT, int K, int TWC, bool WAVE, class Lay>
 __device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
                                            Lay lay, int c, int j, bool act) {
     constexpr int Tc = N / E;
@@ -329,7 +345,7 @@ __device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (
 #pragma unroll
                 for (int r = 0; r < (HZ ? (R + 1) / 2 : R); ++r) v[k][q][r] = reg[k][q + r * NB];
     } else {
-        __syncthreads();
+        stage_sync<WAVE>();
         if (act) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
@@ -360,7 +376,7 @@ __device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (
 #pragma unroll
                 for (int r = 0; r < R; ++r) reg[k][q + r * NB] = v[k][q][r];
     } else {
-        __syncthreads();
+        stage_sync<WAVE>();
         if (act) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
@@ -375,22 +391,24 @@ __device__ __forceinline__ void fftk_stage(cplx<T> (&reg)[K][E], const cplx<T> (
     }
 }
 
-template <typename T, int N, int E, bool FWD, bool HZ, int Ns, int KT, int K, int TWC, class Lay>
+template <typename T, int N, int E, bool FWD, bool HZ, int Ns, int KT, int K, int TWC, bool WAVE, class Lay>
 __device__ __forceinline__ void fftk_stages(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
                                             Lay lay, int c, int j, bool act) {
     if constexpr (Ns < N) {
         constexpr int R = cmin(cmin(8, E), N / Ns);
-        fftk_stage<T, N, E, FWD, HZ, Ns, R, KT, K, TWC>(reg, w, lds, region, lay, c, j, act);
-        fftk_stages<T, N, E, FWD, HZ, Ns * R, (Ns == 1 ? KT : KT + (E / R) * (R - 1)), K, TWC>(reg, w, lds, region,
-                                                                                              lay, c, j, act);
+        fftk_stage<T, N, E, FWD, HZ, Ns, R, KT, K, TWC, WAVE>(reg, w, lds, region, lay, c, j, act);
+        fftk_stages<T, N, E, FWD, HZ, Ns * R, (Ns == 1 ? KT : KT + (E / R) * (R - 1)), K, TWC, WAVE>(
+            reg, w, lds, region, lay, c, j, act);
     }
 }
 
-template <typename T, int N, int E, bool FWD, bool HZ, int K, int TWC, class Lay>
+// WAVE: as for fft_regs, the threads and LDS regions of these transforms
+// belong to one wave, whose stages then synchronise within the wave.
+template <typename T, int N, int E, bool FWD, bool HZ, int K, int TWC, bool WAVE = false, class Lay>
 __device__ __forceinline__ void fft_regs_k(cplx<T> (&reg)[K][E], const cplx<T> (&w)[TWC], cplx<T>* lds, int region,
                                            Lay lay, int c, int j, bool act = true) {
     static_assert(N % E == 0, "E must divide N");
-    fftk_stages<T, N, E, FWD, HZ, 1, 0, K, TWC>(reg, w, lds, region, lay, c, j, act);
+    fftk_stages<T, N, E, FWD, HZ, 1, 0, K, TWC, WAVE>(reg, w, lds, region, lay, c, j, act);
 }
 
 // Full transform of length N on the register distribution described above.
@@ -398,12 +416,16 @@ __device__ __forceinline__ void fft_regs_k(cplx<T> (&reg)[K][E], const cplx<T> (
 // block must call it (it contains barriers when N > E); threads with act ==
 // false (whole waves) take part in the barriers without touching LDS. With
 // HZ the upper half of the input is zero padding and its registers are not read.
-template <typename T, int N, int E, bool FWD, bool HZ = false, class Lay>
+// WAVE: the N/E threads of each transform are consecutive lanes of one wave
+// and its LDS region is touched by no other wave, so the stages synchronise
+// within the wave only (see stage_sync).
+template <typename T, int N, int E, bool FWD, bool HZ = false, bool WAVE = false, class Lay>
 __device__ __forceinline__ void fft_regs(cplx<T> (&reg)[E], cplx<T>* lds, Lay lay, int c, int j,
                                          const cplx<T>* __restrict__ tw, bool act = true) {
     static_assert(N % E == 0, "E must divide N");
     static_assert(!HZ || E >= 2, "a zero upper half needs two elements per thread");
-    fft_stages<T, N, E, FWD, 1, HZ>(reg, lds, lay, c, j, tw, act);
+    static_assert(!WAVE || (N / E <= 64 && 64 % (N / E) == 0), "a wave-local transform fits one wave");
+    fft_stages<T, N, E, FWD, 1, HZ, WAVE>(reg, lds, lay, c, j, tw, act);
 }
 
 }  // namespace dds

@@ -60,11 +60,15 @@ __global__ void __launch_bounds__(512) k_x_r2c(const T* __restrict__ in, cplx<T>
             reg[m] = {a, b};
         }
     }
-    fft_regs<T, M, E, true>(reg, lds, lay, rl, j, tw + (M - 1));
-    __syncthreads();
+    // a row's Tc threads (Tc <= 64 for every planned length) are consecutive
+    // lanes of one wave and its LDS row is its own: the transform and the
+    // split synchronise within the wave
+    constexpr bool WV = Tc <= 64;
+    fft_regs<T, M, E, true, false, WV>(reg, lds, lay, rl, j, tw + (M - 1));
+    stage_sync<WV>();
 #pragma unroll
     for (int m = 0; m < E; ++m) lds[lay(j + Tc * m, rl)] = reg[m];
-    __syncthreads();
+    stage_sync<WV>();
     if (!valid) return;
     cplx<T>* dst = out + row * out_stride;
     const cplx<T>* tw2 = tw + (2 * M - 1);
@@ -110,8 +114,9 @@ __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T
         const int k = j + Tc * m;
         lds[lay(k, rl)] = valid ? src[k] : cplx<T>{T(0), T(0)};
     }
+    constexpr bool WV = Tc <= 64;          // the row is its wave's own (see k_x_r2c)
     if (j == 0) lds[lay(M, rl)] = valid ? src[M] : cplx<T>{T(0), T(0)};
-    __syncthreads();
+    stage_sync<WV>();
     const cplx<T>* tw2 = tw + (2 * M - 1);
     cplx<T> reg[E];
 #pragma unroll
@@ -123,7 +128,7 @@ __global__ void __launch_bounds__(512) k_x_c2r(const cplx<T>* __restrict__ in, T
         const cplx<T> wd = twmul<false>(csub(xk, xm), tw2[k]);   // exp(+2 pi i k/P) (X[k] - conj X[M-k])
         reg[m] = {e.x - wd.y, e.y + wd.x};                       // e + i wd
     }
-    fft_regs<T, M, E, false>(reg, lds, lay, rl, j, tw + (M - 1));
+    fft_regs<T, M, E, false, false, WV>(reg, lds, lay, rl, j, tw + (M - 1));
     if (!valid) return;
     T* dst = out + row * out_stride;
     if (pairs) {        // rows aligned to a pair of reals and n_out even

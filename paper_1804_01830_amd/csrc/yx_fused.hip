@@ -159,7 +159,9 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
             reg[m] = {e.x - wd.y, e.y + wd.x};                       // e + i wd
         }
         __syncthreads();                             // the plane is read: its LDS serves the x exchanges
-        fft_regs<T, M, EX, false>(reg, lds, RowPad{xld, xsh}, y, jx, twl);
+        // each row's TCX threads are consecutive lanes of one wave with an LDS
+        // row of their own: its stages synchronise within the wave
+        fft_regs<T, M, EX, false, false, true>(reg, lds, RowPad{xld, xsh}, y, jx, twl);
         if (row_ok) {
             T* dst = out + plane * (int64_t)ny * nx + (int64_t)y * nx;
             if (pairs) {
@@ -253,11 +255,15 @@ __global__ void __launch_bounds__(kYXThreads) k_xy_fwd(const float* __restrict__
 #pragma unroll
         for (int m = 0; m < EX; ++m) reg[m] = m < EL ? nxt[m] : cplx<T>{T(0), T(0)};
         const RowPad lay{xld, xsh};
-        fft_regs<T, M, EX, true, HX>(reg, lds, lay, yr, j, twl);
+        // the previous plane's column rounds are done with the LDS; from here
+        // to the split, each row's TCX threads (consecutive lanes of one wave)
+        // work on an LDS row of their own and synchronise within the wave
         __syncthreads();
+        fft_regs<T, M, EX, true, HX, true>(reg, lds, lay, yr, j, twl);
+        stage_sync<true>();
 #pragma unroll
         for (int m = 0; m < EX; ++m) lds[lay(j + TCX * m, yr)] = reg[m];
-        __syncthreads();
+        stage_sync<true>();
         {
             const T half = T(0.5);
             cplx<T> xs[EX];
@@ -327,8 +333,7 @@ __global__ void __launch_bounds__(kYXThreads) k_xy_fwd(const float* __restrict__
             }
             c0 += ncols;
         }
-        // (no barrier here: the next plane's first LDS write follows the barrier
-        // inside its first row-transform stage)
+        // (the next plane's row transforms start with a barrier)
     }
 }
 

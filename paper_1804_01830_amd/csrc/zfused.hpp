@@ -31,6 +31,23 @@ __device__ __forceinline__ void z_block_coords(int blk, int nt, int P, int& tile
     }
 }
 
+// The last kx column, kx = M = Px/2 (the Nyquist column of the real-to-complex
+// x spectra), is Hermitian along y because the stress is real: at every z its
+// values at ky and Py - ky are complex conjugates. The block at 0 < ky < Py/2
+// writes both; at ky > Py/2 that column is not written, and a block whose tile
+// holds column M alone (tile * tk == M) does no work there.
+struct NyquistRole {
+    bool skip_block;    // the whole block has nothing to write
+    bool own;           // this lane writes its column at ky
+    bool mirror;        // this lane also writes the conjugate at Py - ky
+};
+__device__ __forceinline__ NyquistRole nyquist_role(int tile, int tk, int col, int ky, bool valid, const ZGeom& g) {
+    const int m = g.ncols - 1;
+    const bool nyq = valid && col == m;
+    const bool upper = 2 * ky > g.nky;
+    return {tile * tk == m && upper, valid && !(nyq && upper), nyq && ky > 0 && 2 * ky < g.nky};
+}
+
 // ----------------------------------------------------------------------------
 // Fused z pass, single-group form. A block owns `tk` consecutive kx columns at
 // one ky and one group of Tc * tk threads. For every realisation b it
@@ -95,6 +112,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
     const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
     const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
     cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
+    const NyquistRole nq = nyquist_role(tile, tk, col, ky, valid, g);
+    if (nq.skip_block) return;                   // uniform over the block, before any barrier
+    cplx<T>* mir_b = out + (int64_t)(g.nky - ky) * g.oos + colc;
 
 #define DDS_LOAD_RHO(DST, BB, CH)                                                          \
     {                                                                                      \
@@ -234,12 +254,20 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             fft_regs_k<T, N, E, false, false, 1>(acc[v], twr, lds, 0, lay, c, j);
-            if (valid) {
+            if (nq.own) {
                 cplx<T>* dst = out_b + (int64_t)(b * 6 + v) * g.oqs;
 #pragma unroll
                 for (int m = 0; m < EH; ++m) {
                     const int z = j + Tc * m;
                     if (z < g.nz) dst[z * ors] = acc[v][0][m];
+                }
+            }
+            if (nq.mirror) {
+                cplx<T>* dst = mir_b + (int64_t)(b * 6 + v) * g.oqs;
+#pragma unroll
+                for (int m = 0; m < EH; ++m) {
+                    const int z = j + Tc * m;
+                    if (z < g.nz) dst[z * ors] = cconj(acc[v][0][m]);
                 }
             }
         }
@@ -266,10 +294,15 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
 // waits for it alone, and the next realisation's density before the inverse
 // transforms, so its latency overlaps them.
 // ----------------------------------------------------------------------------
-template <typename T, int N, int E, int NC>
+// WV: each group is exactly one wave (tk Tc = 64) and owns its LDS region
+// for both transforms (one stress component per group, NC > 3): the stages of
+// its transforms synchronise within the wave, and the block meets only to
+// publish the channel spectra and after the contraction has read them.
+template <typename T, int N, int E, int NC, bool WV>
 __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
                                                    const T* __restrict__ spec, ZGeom g,
                                                    const cplx<T>* __restrict__ tw, int tk, int ld) {
+    static_assert(!WV || NC > 3, "wave-local groups need one stress component and one LDS region per group");
     constexpr int Tc = N / E;
     constexpr int OPG = NC == 3 ? 2 : 1;   // stress components per group
     constexpr int EH = (E + 1) / 2;        // elements that can hold data rows (z < N/2)
@@ -301,6 +334,9 @@ __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ i
     const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
     const int ors = (int)g.ors;                      // in-block offsets fit in 32 bits
     cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
+    const NyquistRole nq = nyquist_role(tile, tk, col, ky, valid, g);
+    if (nq.skip_block) return;                   // uniform over the block, before any barrier
+    cplx<T>* mir_b = out + (int64_t)(g.nky - ky) * g.oos + colc;
 
     cplx<T> fw[1][E];
     {
@@ -348,7 +384,7 @@ __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ i
 
     for (int b = 0; b < g.B; ++b) {
         // 1. forward transform of channel grp; its spectrum to LDS region grp
-        fft_regs_k<T, N, E, true, HZ, 1>(fw, twr, lds + grp * region, region, lay, c, j);
+        fft_regs_k<T, N, E, true, HZ, 1, TWC, WV>(fw, twr, lds + grp * region, region, lay, c, j);
         __syncthreads();                             // the last stage's LDS reads are done
 #pragma unroll
         for (int m = 0; m < E; ++m) lds[grp * region + lay(j + Tc * m, c)] = fw[0][m];
@@ -375,9 +411,11 @@ __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ i
 #pragma unroll
             for (int m = 0; m < EH; ++m) fw[0][m] = buf_cplx<T>(rr, r_lane, m * r_step);
         }
-        // inverse transforms (their first stage's barrier precedes any LDS write)
-        fft_regs_k<T, N, E, false, false, OPG>(acc, twr, lds + OPG * grp * region, region, lay, c, j);
-        if (valid && has_v) {
+        // inverse transforms (their first stage's barrier precedes any LDS write;
+        // wave-local stages have none, so the block meets here first)
+        if constexpr (WV) __syncthreads();
+        fft_regs_k<T, N, E, false, false, OPG, TWC, WV>(acc, twr, lds + OPG * grp * region, region, lay, c, j);
+        if (nq.own && has_v) {
 #pragma unroll
             for (int k = 0; k < OPG; ++k) {
                 cplx<T>* dst = out_b + (int64_t)(b * 6 + OPG * grp + k) * g.oqs;
@@ -385,6 +423,17 @@ __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ i
                 for (int m = 0; m < EH; ++m) {
                     const int z = j + Tc * m;
                     if (z < g.nz) dst[z * ors] = acc[k][m];
+                }
+            }
+        }
+        if (nq.mirror && has_v) {
+#pragma unroll
+            for (int k = 0; k < OPG; ++k) {
+                cplx<T>* dst = mir_b + (int64_t)(b * 6 + OPG * grp + k) * g.oqs;
+#pragma unroll
+                for (int m = 0; m < EH; ++m) {
+                    const int z = j + Tc * m;
+                    if (z < g.nz) dst[z * ors] = cconj(acc[k][m]);
                 }
             }
         }
@@ -400,8 +449,15 @@ static void z_launch(int64_t blocks, int tk, const cplx<T>* in, cplx<T>* out, co
     const int ld = z_lds_ld(tk, (int)sizeof(T));
     const dim3 block(groups * tk * (L / E));
     if constexpr (GROUPED) {
-        hipLaunchKernelGGL((k_z_grouped<T, L, E, NC>), dim3((unsigned)blocks), block, lds, s, in, out, spec, g, tw, tk,
-                           ld);
+        if constexpr (NC > 3 && L / E <= 64 && 64 % (L / E) == 0) {
+            if (tk * (L / E) == 64) {
+                hipLaunchKernelGGL((k_z_grouped<T, L, E, NC, true>), dim3((unsigned)blocks), block, lds, s, in, out,
+                                   spec, g, tw, tk, ld);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_z_grouped<T, L, E, NC, false>), dim3((unsigned)blocks), block, lds, s, in, out, spec, g,
+                           tw, tk, ld);
     } else if constexpr (L >= 2 && L <= 256) {
         if (z_stage_spec(L, tk, NC, g.nkz_s, g.B, (int)sizeof(T))) {
             lds += z_stage_bytes(tk, NC, g.nkz_s, (int)sizeof(T));
