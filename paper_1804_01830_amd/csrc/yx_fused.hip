@@ -11,8 +11,9 @@
 //   1. the kx columns are transformed along y (8 elements per thread) in
 //      rounds of 16-column groups; each group exchanges through its own LDS
 //      region placed after the plane columns already finished, so a round
-//      takes up to two groups, as many as the remaining LDS holds (32, 32, 32,
-//      32 and 1 columns at Py = 256, M = 128);
+//      takes up to two groups, as many as the remaining LDS holds (4 rounds of
+//      32 columns at Py = 256, M = 128: columns 0 and M, whose transforms are
+//      real, travel together as X[0] + i X[M]);
 //      rows y < Ny go to the plane, stored as column c at c (Py/2) + (y ^ (c & 15))
 //      (the XOR spreads a group's 16 columns over the banks);
 //   2. each row is combined into Z'[k] = (X[k] + conj X[M-k]) + i exp(+2 pi i k / P)
@@ -22,7 +23,8 @@
 // of the next round, and of the next plane's first round, are requested
 // before the current transforms so their latency overlaps them. The
 // arithmetic is that of the two plain passes at element classes 8 (y) and 16
-// (x), so results are identical.
+// (x), except for the packed columns 0 and M (so the results agree with the
+// separate passes to rounding, not bit for bit).
 //
 // Twiddles. Vector-memory loads and stores complete in issue order, so a
 // twiddle load issued after a column prefetch (or after a round's stores)
@@ -61,7 +63,7 @@ __device__ __forceinline__ void yx_round(int c0, int& groups, int& ncols) {
     constexpr int CAP = kYXLds / (int)sizeof(cplx<float>);
     groups = (CAP - c0 * PLD) / (PY * GC);
     if (groups > kYXThreads / GT) groups = kYXThreads / GT;
-    ncols = groups * GC < M + 1 - c0 ? groups * GC : M + 1 - c0;
+    ncols = groups * GC < M - c0 ? groups * GC : M - c0;
     groups = (ncols + GC - 1) / GC;
 }
 
@@ -71,7 +73,6 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
                                                        const cplx<float>* __restrict__ tw, int xld, int xsh,
                                                        int pairs, double* __restrict__ rowsq) {
     using T = float;
-    constexpr int M1 = M + 1;
     constexpr int PLD = PY / 2;                          // plane column stride: rows y < Py/2
     constexpr int GC = 16, EY = 8, TCY = PY / EY;        // y: 16 columns per group, Tc threads per column
     constexpr int GT = GC * TCY;                         // threads per group
@@ -90,15 +91,26 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
     // The block walks over planes; the loads of the next round (or of the next
     // plane's first round) are requested before the current transform.
     cplx<T> nxt[EY];
+    // Columns 0 and M (kx = 0 and the Nyquist column) are Hermitian along ky,
+    // so their inverse transforms are real: they travel as the one column
+    // X[0] + i X[M] and come out as Re = column 0, Im = column M (the z pass
+    // writes column M exactly Hermitian; column 0's rounding-level imaginary
+    // part is dropped). The rounds cover columns 0 .. M-1.
     auto load_cols = [&](int64_t pl, int c0) {
         int groups, ncols;
         yx_round<PY, M, GC, GT>(c0, groups, ncols);
         const int c = c0 + gi * GC + cl;
-        const bool valid = gi < groups && c < M1;
+        const bool valid = gi < groups && c < M;
         const cplx<T>* src = in + pl * (int64_t)PY * wx;
 #pragma unroll
-        for (int m = 0; m < EY; ++m)
-            nxt[m] = valid ? src[(int64_t)(jy + TCY * m) * wx + c] : cplx<T>{T(0), T(0)};
+        for (int m = 0; m < EY; ++m) {
+            const int64_t r = (int64_t)(jy + TCY * m) * wx;
+            nxt[m] = valid ? src[r + c] : cplx<T>{T(0), T(0)};
+            if (valid && c == 0) {
+                const cplx<T> xm = src[r + M];
+                nxt[m] = {nxt[m].x - xm.y, nxt[m].y + xm.x};
+            }
+        }
     };
     int64_t plane = blockIdx.x;
     if (plane < nplanes) load_cols(plane, 0);
@@ -117,17 +129,17 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
         // the x-phase tables, written to the top of LDS after the rounds (which
         // use all of it): exp(-2 pi i k / M) and exp(-2 pi i k / P), k < M
         const cplx<T> tv = t < 2 * M ? tw[t < M ? (M - 1) + t : (2 * M - 1) + (t - M)] : cplx<T>{T(0), T(0)};
-        for (int c0 = 0; c0 < M1;) {
+        for (int c0 = 0; c0 < M;) {
             int groups, ncols;
             yx_round<PY, M, GC, GT>(c0, groups, ncols);
             asm volatile("" : "+v"(jy));                  // per round, as above
             const bool act = gi < groups;                // whole waves
             const int c = c0 + gi * GC + cl;
-            const bool valid = act && c < M1;
+            const bool valid = act && c < M;
             cplx<T> reg[1][EY];
 #pragma unroll
             for (int m = 0; m < EY; ++m) reg[0][m] = nxt[m];
-            if (c0 + ncols < M1) load_cols(plane, c0 + ncols);
+            if (c0 + ncols < M) load_cols(plane, c0 + ncols);
             cplx<T>* scratch = lds + c0 * PLD + (act ? gi : 0) * (PY * GC);
             fft_regs_k<T, PY, EY, false, false, 1, TWY>(reg, twy, scratch, 0, ColMajor{GC}, cl, jy, act);
             __syncthreads();                             // the groups' last exchange reads are done
@@ -152,8 +164,12 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
             const int k = jx + TCX * m;
             const int km = M - k;
             const int yr = row_ok ? y : 0;
-            const cplx<T> xk = lds[k * PLD + (yr ^ (k & 15))];
-            const cplx<T> xm = cconj(lds[km * PLD + (yr ^ (km & 15))]);
+            cplx<T> xk = lds[k * PLD + (yr ^ (k & 15))];
+            cplx<T> xm = cconj(lds[(km & (M - 1)) * PLD + (yr ^ (km & 15))]);
+            if (m == 0 && k == 0) {                  // X[0] and X[M], both real, packed in column 0
+                xm = {xk.y, T(0)};
+                xk = {xk.x, T(0)};
+            }
             const cplx<T> e = cadd(xk, xm);
             const cplx<T> wd = twmul<false>(csub(xk, xm), twl[M + k]);   // exp(+2 pi i k/P) (X[k] - conj X[M-k])
             reg[m] = {e.x - wd.y, e.y + wd.x};                       // e + i wd
