@@ -719,7 +719,8 @@ def summary(r32, r64, w, C, B, periodic):
     nx, ny, nz = w["n"]
     cells = B * nx * ny * nz
     z_ms = r32["passes"]["z_fused"]
-    kname = "k_z_grouped" if info.z_groups > 1 else "k_z_serial"
+    wave = info.z_groups == 1 and info.ez == 8 and info.padded[2] == 64 and info.precision == 32
+    kname = "k_z_grouped" if info.z_groups > 1 else ("k_z_wave" if wave else "k_z_serial")
     zmir = z_pass_bytes(info, w["n"], C, B, elem)
     from paper_1804_01830_amd import profiling as Pf
     traffic = Pf.stored_traffic(os.path.join(ROOT, "profiles"), w["name"], B, kname)

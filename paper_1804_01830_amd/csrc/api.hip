@@ -572,6 +572,9 @@ bool col_ok(const Shape& s, int N, int tk, int ev) {
            (size_t)N * tk * 2 * s.elem <= kMaxLds;
 }
 bool z_ok(const Shape& s, int tk, int ev, int groups) {
+    if (s.elem == 4 && s.P[2] == 64 && ev == 8)         // the wave form: fixed tile, one group
+        return z_wave_form(s.P[2], ev, groups, s.elem) && tk == kZWaveTile &&
+               z_wave_lds_bytes(s.P[2], s.C, s.nkzs, s.B) <= kMaxLds;
     return tk >= 1 && z_groups_ok(groups, s.C) && ev_z_ok(s.P[2], ev, s.elem) &&
            z_threads(s.P[2], groups, tk, ev) <= z_max_threads(groups) &&
            z_lds_bytes(s.P[2], tk, s.C, groups, s.elem) <= kMaxLds;

@@ -185,6 +185,11 @@ int default_z_groups(int N, int C, int B, int elem_bytes);
 int z_max_threads(int groups);
 size_t z_stage_bytes(int tk, int C, int nkz, int elem_bytes);
 bool z_stage_spec(int N, int tk, int C, int nkz, int B, int elem_bytes);
+// The wave form of the fused z pass (FP32, z length 64, element class 8, one
+// thread group): one wave per tile of kZWaveTile columns and realisation.
+constexpr int kZWaveTile = 8;
+bool z_wave_form(int N, int ev, int groups, int elem_bytes);
+size_t z_wave_lds_bytes(int N, int C, int nkz, int B);
 
 // Fused z launch for C = NC channels and one form (zfused.hpp; instantiated
 // per form and precision in z_serial_f32.hip, z_grouped_f64.hip, ...).

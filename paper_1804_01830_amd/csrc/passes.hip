@@ -250,7 +250,20 @@ constexpr int kLongZ = 256;              // shortest z length with the larger cl
 bool ev_z_ok(int N, int ev, int elem_bytes) {
     const int b = base_ev_z(elem_bytes);
     if (ev == b) return true;
+    if (elem_bytes == 4 && N == 64 && ev == 8) return true;          // the wave form
     return N >= kLongZ && ev <= 16 && (ev == 2 * b || ev == 4 * b || ev == 8 * b);
+}
+
+// The wave form: FP32, z length 64, element class 8, one thread group; its
+// tile is kZWaveTile columns (8 lanes each: one wave).
+bool z_wave_form(int N, int ev, int groups, int elem_bytes) {
+    return elem_bytes == 4 && N == 64 && ev == 8 && groups == 1;
+}
+// Its LDS: the staged spectrum tile (16-byte aligned) and one 64 x 8 exchange
+// region per wave (min(B, 4) waves).
+size_t z_wave_lds_bytes(int N, int C, int nkz, int B) {
+    const int wpb = B >= 4 ? 4 : (B >= 2 ? 2 : 1);
+    return (z_stage_bytes(kZWaveTile, C, nkz, 4) + 15) / 16 * 16 + (size_t)wpb * N * kZWaveTile * 8;
 }
 
 // The base class, or the smallest larger one with which a block of one
@@ -498,9 +511,14 @@ void launch_z_fused(int N, int ev, int groups, const cplx<T>* in, cplx<T>* out, 
     if (blocks > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
     if (!ev_z_ok(N, ev, (int)sizeof(T))) fail(DDSTRESS_E_INVALID, "z element class not supported for this length");
     if (!z_groups_ok(groups, g.C)) fail(DDSTRESS_E_INVALID, "z thread groups must be 1 or the channel count");
-    if (tk < 1 || z_threads(N, groups, tk, ev) > z_max_threads(groups) ||
-        z_lds_bytes(N, tk, g.C, groups, (int)sizeof(T)) > 64 * 1024)
+    if (ev == 8 && N == 64 && sizeof(T) == 4) {
+        if (!z_wave_form(N, ev, groups, 4) || tk != kZWaveTile || z_wave_lds_bytes(N, g.C, g.nkz_s, g.B) > 64 * 1024)
+            fail(DDSTRESS_E_INVALID, "the wave form of the fused z pass takes one thread group, 8-column tiles "
+                                     "and 64 KiB of LDS");
+    } else if (tk < 1 || z_threads(N, groups, tk, ev) > z_max_threads(groups) ||
+               z_lds_bytes(N, tk, g.C, groups, (int)sizeof(T)) > 64 * 1024) {
         fail(DDSTRESS_E_INVALID, "fused z block exceeds the thread or LDS limit");
+    }
     // one instance per channel count: the channel loops are unrolled
     const bool grouped = groups != 1;
     switch (g.C) {

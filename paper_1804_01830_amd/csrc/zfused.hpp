@@ -48,6 +48,50 @@ __device__ __forceinline__ NyquistRole nyquist_role(int tile, int tk, int col, i
     return {tile * tk == m && upper, valid && !(nyq && upper), nyq && ky > 0 && 2 * ky < g.nky};
 }
 
+// Copy a block's spectrum tile [c][v][kz][TK] (nkz rows kz, NC channels,
+// six components) into LDS as rows kz of [c][v][TK] values with the row
+// stride (6 NC + 1) TK, applying the y-mirror sign of the odd planes (bit
+// c 6 + v of sgn_y) when flip_y. NT threads (tid < NT) copy 16-byte pieces,
+// up to 16 loads each in flight before their stores; a piece never straddles
+// a source row (TK is a multiple of its width). The caller synchronises.
+template <typename T, int NC, int TK, int NT>
+__device__ __forceinline__ void stage_spectrum_tile(T* s_l, __amdgpu_buffer_rsrc_t srs, int nkz, bool flip_y,
+                                                    uint64_t sgn_y, int tid) {
+    constexpr int KS = (6 * NC + 1) * TK;
+    constexpr int VW = 16 / (int)sizeof(T);
+    constexpr int CH = 16;
+    const int n_vals = NC * 6 * nkz * TK;
+    const float rcp = 1.0f / (float)nkz;
+    for (int k0 = 0; k0 * NT * VW < n_vals; k0 += CH) {
+        uint4 piece[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+            piece[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(srs, (tid + (k0 + k) * NT) * 16,
+                                                                                    0, 0));
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int i = (tid + (k0 + k) * NT) * VW;    // first value of the piece
+            if (i < n_vals) {
+                const int r = i / TK, cc = i % TK;
+                int cv = (int)((float)r * rcp);
+                if (cv * nkz > r) --cv;
+                if ((cv + 1) * nkz <= r) ++cv;
+                const int kz = r - cv * nkz;
+                const bool neg = flip_y && ((sgn_y >> cv) & 1);      // cv = c 6 + v
+                uint4 q = piece[k];
+                if (neg) {                                              // flip the sign bits
+                    if constexpr (sizeof(T) == 4) {
+                        q.x ^= 0x80000000u; q.y ^= 0x80000000u; q.z ^= 0x80000000u; q.w ^= 0x80000000u;
+                    } else {
+                        q.y ^= 0x80000000u; q.w ^= 0x80000000u;
+                    }
+                }
+                *reinterpret_cast<uint4*>(s_l + kz * KS + cv * TK + cc) = q;
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Fused z pass, single-group form. A block owns `tk` consecutive kx columns at
 // one ky and one group of Tc * tk threads. For every realisation b it
@@ -143,42 +187,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
         }
     }
     if constexpr (SL) {
-        // copy [c][v][kz][TK] -> rows kz of [c][v][TK] in 16-byte pieces: up to
-        // 16 loads per thread are in flight before their stores; a piece never
-        // straddles a source row (TK is a multiple of its width)
-        constexpr int VW = 16 / (int)sizeof(T);
-        constexpr int NT = TK * Tc;
-        constexpr int CH = 16;
-        const int n_vals = NC * 6 * nkz * TK;
-        const float rcp = 1.0f / (float)nkz;
-        for (int k0 = 0; k0 * NT * VW < n_vals; k0 += CH) {
-            uint4 piece[CH];
-#pragma unroll
-            for (int k = 0; k < CH; ++k)
-                piece[k] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
-                                                         srs, ((int)threadIdx.x + (k0 + k) * NT) * 16, 0, 0));
-#pragma unroll
-            for (int k = 0; k < CH; ++k) {
-                const int i = ((int)threadIdx.x + (k0 + k) * NT) * VW;    // first value of the piece
-                if (i < n_vals) {
-                    const int r = i / TK, cc = i % TK;
-                    int cv = (int)((float)r * rcp);
-                    if (cv * nkz > r) --cv;
-                    if ((cv + 1) * nkz <= r) ++cv;
-                    const int kz = r - cv * nkz;
-                    const bool neg = flip_y && ((g.sgn_y >> cv) & 1);      // cv = c 6 + v
-                    uint4 q = piece[k];
-                    if (neg) {                                              // flip the sign bits
-                        if constexpr (sizeof(T) == 4) {
-                            q.x ^= 0x80000000u; q.y ^= 0x80000000u; q.z ^= 0x80000000u; q.w ^= 0x80000000u;
-                        } else {
-                            q.y ^= 0x80000000u; q.w ^= 0x80000000u;
-                        }
-                    }
-                    *reinterpret_cast<uint4*>(s_l + kz * KS + cv * TK + cc) = q;
-                }
-            }
-        }
+        stage_spectrum_tile<T, NC, TK, TK * Tc>(s_l, srs, nkz, flip_y, g.sgn_y, (int)threadIdx.x);
         __syncthreads();
     }
 #define DDS_LOAD_SPEC(DST, CH)                                                             \
@@ -268,6 +277,139 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
                 for (int m = 0; m < EH; ++m) {
                     const int z = j + Tc * m;
                     if (z < g.nz) dst[z * ors] = cconj(acc[v][0][m]);
+                }
+            }
+        }
+    }
+}
+
+
+// ----------------------------------------------------------------------------
+// Fused z pass, wave form (FP32, z length 64, 8 elements per thread). A block
+// owns TK = 8 consecutive kx columns at one ky, stages their spectrum tile in
+// LDS once (as the single-group form does) and runs WPB waves; wave w
+// evaluates realisations b = w, w + WPB, ... on its own. Its 64 lanes hold the
+// 8 columns with 8 lanes each (lane = 8 j + c: rows j + 8 m of column c), so
+// a wave load or store covers 8 rows of 64 contiguous bytes, and every
+// transform's lanes are in the wave: the stages exchange through a
+// wave-private LDS region and synchronise within the wave (no workgroup
+// barrier after the staging). Per realisation the C density columns are
+// transformed along z (rows z >= N/2 are padding and are not loaded) and kept
+// in registers; then for each stress component
+//     sigma^_v(k) = sum_c i S_{v,c}(k) rho^_c(k)      (K^ = i S, K odd),
+// summed over c in increasing order, is transformed back along z and rows
+// z < nz are written. The next realisation's density is requested before the
+// inverse transforms. The radix sequence (8, 8) differs from the other forms'
+// (4, 4, 4), so results agree with them to rounding, not bit for bit.
+// ----------------------------------------------------------------------------
+template <typename T, int N, int E, int NC, int WPB>
+__global__ void __launch_bounds__(64 * WPB) k_z_wave(const cplx<T>* __restrict__ in, cplx<T>* __restrict__ out,
+                                                     const T* __restrict__ spec, ZGeom g,
+                                                     const cplx<T>* __restrict__ tw) {
+    constexpr int TK = kZWaveTile;
+    constexpr int Tc = N / E;
+    static_assert(Tc * TK == 64, "the tile's columns fill one wave");
+    constexpr int EH = (E + 1) / 2;        // elements that can hold data rows (z < N/2)
+    constexpr bool HZ = true;              // the upper half of every input column is padding
+    constexpr int KS = (6 * NC + 1) * TK;  // staged row stride (values)
+    extern __shared__ unsigned char smem_raw[];
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    const int c = lane % TK, j = lane / TK;
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    int tile, ky;
+    z_block_coords(blk, g.ntiles, g.nky, tile, ky);
+    const int col = tile * TK + c;
+    const bool valid = col < g.ncols;
+    const int colc = valid ? col : 0;
+    const NyquistRole nq = nyquist_role(tile, TK, col, ky, valid, g);
+    if (nq.skip_block) return;                   // uniform over the block, before any barrier
+    const int ors = (int)g.ors;
+    // spectrum tile (see the single-group form): rows kyc, mirrored rows signed
+    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
+    const int kyc = flip_y ? g.nky - ky : ky;
+    const bool zc = g.nkz_s < N;
+    const int nkz = g.nkz_s;
+    const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * TK;
+    const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * TK * sizeof(T)));
+    T* s_l = reinterpret_cast<T*>(smem_raw);
+    const size_t stage_bytes = ((size_t)nkz * KS * sizeof(T) + 15) / 16 * 16;
+    cplx<T>* xw = reinterpret_cast<cplx<T>*>(smem_raw + stage_bytes) + w * (N * TK);    // this wave's exchanges
+    const ColMajor lay{TK};
+    // density rows z < nz; rows >= nz lie beyond the resource and read as zero;
+    // lanes of padding columns read the tile's first column
+    const cplx<T>* in_b = in + (int64_t)ky * g.ios + (int64_t)tile * TK;
+    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
+    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
+    const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
+    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
+    cplx<T>* mir_b = out + (int64_t)(g.nky - ky) * g.oos + colc;
+
+    cplx<T> nxt[NC][EH];
+    auto load_rho = [&](int b) {
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) {
+            const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_b + (int64_t)(b * g.C + ch) * g.iqs, plane_bytes);
+#pragma unroll
+            for (int m = 0; m < EH; ++m) nxt[ch][m] = buf_cplx<T>(rr, r_lane, m * r_step);
+        }
+    };
+    if (w < g.B) load_rho(w);
+    constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
+    cplx<T> twr[TWC];
+    load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
+    // staged row of each element (see the single-group form)
+    int s_row[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        s_row[m] = j * KS + c + Tc * m * KS;
+        if (2 * m >= E) {
+            s_row[m] = zc ? (Tc - j) * KS + c + Tc * (E - 1 - m) * KS : s_row[m];
+            asm volatile("" : "+v"(s_row[m]));
+        }
+    }
+    stage_spectrum_tile<T, NC, TK, 64 * WPB>(s_l, srs, nkz, flip_y, g.sgn_y, (int)threadIdx.x);
+    __syncthreads();
+
+    for (int b = w; b < g.B; b += WPB) {
+        cplx<T> rho[NC][1][E];
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) {
+#pragma unroll
+            for (int m = 0; m < EH; ++m) rho[ch][0][m] = nxt[ch][m];
+            fft_regs_k<T, N, E, true, HZ, 1, TWC, true>(rho[ch], twr, xw, 0, lay, c, j);
+        }
+        if (b + WPB < g.B) load_rho(b + WPB);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            cplx<T> acc[1][E];
+#pragma unroll
+            for (int m = 0; m < E; ++m) acc[0][m] = {T(0), T(0)};
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) {
+                const T sz = ((g.sgn_z >> (ch * 6 + v)) & 1) ? T(-1) : T(1);    // staged values carry the y sign
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const T sv = s_l[s_row[m] + (ch * 6 + v) * TK];
+                    const T sval = (zc && 2 * m >= E) ? sz * sv : sv;
+                    acc[0][m].x -= sval * rho[ch][0][m].y;
+                    acc[0][m].y += sval * rho[ch][0][m].x;
+                }
+            }
+            fft_regs_k<T, N, E, false, false, 1, TWC, true>(acc, twr, xw, 0, lay, c, j);
+            if (nq.own) {
+                cplx<T>* dst = out_b + (int64_t)(b * 6 + v) * g.oqs;
+#pragma unroll
+                for (int m = 0; m < EH; ++m) {
+                    const int z = j + Tc * m;
+                    if (z < g.nz) dst[z * ors] = acc[0][m];
+                }
+            }
+            if (nq.mirror) {
+                cplx<T>* dst = mir_b + (int64_t)(b * 6 + v) * g.oqs;
+#pragma unroll
+                for (int m = 0; m < EH; ++m) {
+                    const int z = j + Tc * m;
+                    if (z < g.nz) dst[z * ors] = cconj(acc[0][m]);
                 }
             }
         }
@@ -448,7 +590,20 @@ static void z_launch(int64_t blocks, int tk, const cplx<T>* in, cplx<T>* out, co
     size_t lds = z_lds_bytes(L, tk, NC, groups, (int)sizeof(T));
     const int ld = z_lds_ld(tk, (int)sizeof(T));
     const dim3 block(groups * tk * (L / E));
-    if constexpr (GROUPED) {
+    if constexpr (!GROUPED && sizeof(T) == 4 && L == 64 && E == 8) {
+        // the wave form (the only single-group form with 8 elements at length 64)
+        const int wpb = g.B >= 4 ? 4 : (g.B >= 2 ? 2 : 1);
+        const size_t stage = (z_stage_bytes(kZWaveTile, NC, g.nkz_s, 4) + 15) / 16 * 16;
+        const size_t lw = stage + (size_t)wpb * L * kZWaveTile * sizeof(cplx<T>);
+        const dim3 grid((unsigned)blocks);
+        if (wpb == 4)
+            hipLaunchKernelGGL((k_z_wave<T, L, E, NC, 4>), grid, dim3(256), lw, s, in, out, spec, g, tw);
+        else if (wpb == 2)
+            hipLaunchKernelGGL((k_z_wave<T, L, E, NC, 2>), grid, dim3(128), lw, s, in, out, spec, g, tw);
+        else
+            hipLaunchKernelGGL((k_z_wave<T, L, E, NC, 1>), grid, dim3(64), lw, s, in, out, spec, g, tw);
+        (void)tk;
+    } else if constexpr (GROUPED) {
         if constexpr (NC > 3 && L / E <= 64 && 64 % (L / E) == 0) {
             if (tk * (L / E) == 64) {
                 hipLaunchKernelGGL((k_z_grouped<T, L, E, NC, true>), dim3((unsigned)blocks), block, lds, s, in, out,
@@ -506,6 +661,12 @@ template <typename T, int NC, bool GROUPED>
 void z_dispatch(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
                        const cplx<T>* tw, int tk, int64_t blocks, hipStream_t s) {
     constexpr int EV = sizeof(T) == 4 ? 4 : 2;
+    if constexpr (sizeof(T) == 4 && !GROUPED) {
+        if (N == 64 && ev == 8) {
+            z_launch<T, 64, 8, NC, false>(blocks, tk, in, out, spec, g, tw, s);
+            return;
+        }
+    }
     if (ev == EV) z_ev<T, EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
     else if (ev == 2 * EV) z_ev_long<T, 2 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);
     else if (ev == 4 * EV) z_ev_long<T, 4 * EV, NC, GROUPED>(N, in, out, spec, g, tw, tk, blocks, s);

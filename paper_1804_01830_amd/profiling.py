@@ -82,6 +82,9 @@ def _z_shape(line):
     tk = info["tile_z"]
     e = min(pz, info["ez"])
     threads = groups * tk * (pz // e)
+    if groups == 1 and e == 8 and pz == 64:       # the wave form: one wave per realisation, up to four a block
+        b = cfg["batch"]
+        threads = 64 * (4 if b >= 4 else (2 if b >= 2 else 1))
     m1 = info["padded"][0] // 2 + 1
     blocks = ((m1 + tk - 1) // tk) * info["padded"][1]
     return threads, blocks * threads
@@ -93,7 +96,7 @@ def traffic(fetch_dir, write_dir, line, copy_mib):
     for counter, directory in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = [r for r in _csv(directory, "counter_collection.csv") if r["Counter_Name"] == counter]
         z = [float(r["Counter_Value"]) for r in rows
-             if re.search(r"k_z_(serial|grouped)<", r["Kernel_Name"])
+             if re.search(r"k_z_(serial|grouped|wave)<", r["Kernel_Name"])
              and int(r["Workgroup_Size"]) == block and int(r["Grid_Size"]) == grid]
         other = [float(r["Counter_Value"]) for r in rows if "dds::" not in r["Kernel_Name"]]
         if not z or not other:

@@ -365,3 +365,79 @@ def test_kernel_spectrum_is_imaginary(case):
     _say(f"[spectrum] n={case['n']} periodic={case.get('periodic')} max|Re|={info.kernel_real_max:.3e} "
          f"max|Im|={info.kernel_imag_max:.3e} ratio={ratio:.2e}")
     assert info.kernel_imag_max > 0.0 and ratio <= 1e-13
+
+
+# The wave form of the fused z pass (FP32, z length 64: Nz 17..32): one wave
+# per 8-column tile and realisation, forced through the tuning struct, on
+# ragged grids, one to three line directions and batches that leave some
+# waves of a block idle.
+WAVE = {
+    "rand-21x13x20-L1-B3": lambda: W.random_field((21, 13, 20), n_lines=1, batch=3, seed=41, d=(1.0, 1.0, 2.0)),
+    # two line directions whose planes all have a z parity (kz <= 32 stored): the tile fits 64 KiB
+    "rand-9x30x32-L2-B5": lambda: W.random_field((9, 30, 32), batch=5, seed=42, d=(1.0, 1.5, 2.0),
+                                                 lines=[(0.0, 0.0, 1.0), (1.0, 0.0, 0.0)]),
+    "rand-40x24x25-L1-B2-tilt": lambda: W.random_field((40, 24, 25), batch=2, seed=44, d=(1.0, 1.0, 2.0),
+                                                       lines=[TILT]),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _wave_case(name):
+    w = WAVE[name]()
+    ref = np.stack([stress_direct(w["rho"][b], w["d"], w["lines"], w["mu"], w["nu"])
+                    for b in range(w["rho"].shape[0])])
+    return w, ref
+
+
+@pytest.mark.parametrize("name", list(WAVE))
+def test_wave_form_matches_the_oracle(name):
+    import torch
+    from paper_1804_01830_amd import binding as B
+    w, ref = _wave_case(name)
+    nb = w["rho"].shape[0]
+    desc = B.make_desc(w["n"], w["d"], w["mu"], w["nu"], w["lines"], precision=32, batch=nb)
+    d0 = B.Plan(desc).info()
+    assert d0.padded[2] == 64
+    t = B.Tuning()
+    t.rows_x, t.tk_y, t.ex, t.ey = d0.rows_x, d0.tile_y, d0.ex, d0.ey
+    t.tk_z, t.ez, t.z_groups = 8, 8, 1
+    rho = torch.from_numpy(w["rho"]).to("cuda", dtype=torch.float32).contiguous()
+    outs = []
+    for tuning in (t, None):
+        plan = B.Plan(desc, tuning=tuning)
+        info = plan.info()
+        plan.set_density(rho)
+        out = plan.new_output()
+        plan.stress(out)
+        torch.cuda.synchronize()
+        outs.append(out.double().cpu().numpy())
+        if tuning is t:
+            assert (info.ez, info.tile_z, info.z_groups) == (8, 8, 1)
+            # a call on fewer realisations (idle waves in every block)
+            part = torch.empty((1, 6, *rho.shape[2:]), dtype=torch.float32, device="cuda")
+            plan.stress_batch(rho[nb - 1:].contiguous(), part, 1)
+            torch.cuda.synchronize()
+            assert torch.equal(part[0], out[nb - 1])
+        plan.close()
+    comp, whole = rel_l2(outs[0], ref)
+    _say(f"[wave form] {name}: per component {np.array2string(comp, precision=2)} whole {whole:.2e}")
+    assert np.all(comp <= TOL[32]) and whole <= TOL[32]
+    # against the default (single-group, element class 4) form: FP32 rounding apart
+    assert np.linalg.norm(outs[0] - outs[1]) <= 1e-6 * np.linalg.norm(outs[1])
+
+
+def test_wave_form_refuses_other_tiles_groups_and_large_tiles():
+    """The wave form takes 8-column tiles and one thread group, and its
+    staged spectrum tile must fit 64 KiB of LDS (three line directions with
+    no z parity need more)."""
+    from paper_1804_01830_amd import binding as B
+    for lines, bad in (([(0, 0, 1)], ((16, 1), (4, 1), (8, 3))), ([(0, 0, 1), TILT, DIAG], ((8, 1),))):
+        desc = B.make_desc((20, 16, 30), (1, 1, 2), 1.0, 0.3, lines, precision=32, batch=2)
+        d0 = B.Plan(desc).info()
+        for tk, groups in bad:
+            t = B.Tuning()
+            t.rows_x, t.tk_y, t.ex, t.ey = d0.rows_x, d0.tile_y, d0.ex, d0.ey
+            t.tk_z, t.ez, t.z_groups = tk, 8, groups
+            with pytest.raises(B.DDStressError) as e:
+                B.Plan(desc, tuning=t)
+            assert e.value.status == B.E_INVALID
