@@ -148,7 +148,7 @@ def b_pass_bytes(C, B, elem):
     return elem * (13 * C + 24 * C / B + 78)
 
 
-def survey_z_bytes(C, B, cells, elem):
+def five_pass_z_bytes(C, B, cells, elem):
     """Algorithmic HBM bytes of one fused z launch by the five-pass model:
     per cell and realisation it reads the C density columns (4C reals: the
     half spectrum of the padded x-y plane holds about 2N complex values per
@@ -728,7 +728,7 @@ def summary(r32, r64, w, C, B, periodic):
         # the five-pass model assumes padded x and y: the periodic plans transform Nx x Ny planes
         zalg, basis = zmir, "algorithmic bytes of the transforms the plan runs (mirror-compressed spectrum)"
     else:
-        zalg = survey_z_bytes(C, B, nx * ny * nz, elem)
+        zalg = five_pass_z_bytes(C, B, nx * ny * nz, elem)
         basis = "five-pass model: s (4C + 24C/B + 24) per cell (full spectrum read once per launch)"
     achieved = zalg / (z_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
