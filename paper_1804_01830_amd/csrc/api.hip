@@ -118,9 +118,10 @@ Shape make_shape(const ddstress_desc* d) {
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
     set_mirrors(s, predict_mirror(d, 1), predict_mirror(d, 2));
     s.sgn_y = s.sgn_z = 0;
-    // The fused z pass addresses a density plane [Nz][Py][Wx] through one
-    // buffer resource with 32-bit byte offsets: every row it can form (z <
-    // Pz/2) must lie within a signed 32-bit offset.
+    // The fused z pass addresses a density (or stress) group of Nz Py Wx
+    // complex values through buffer resources with 32-bit byte offsets: the
+    // group, bounded here by Pz/2 >= Nz rows, must lie within a signed 32-bit
+    // offset.
     const int64_t zrow_bytes = (int64_t)s.P[1] * s.wx * 2 * s.elem;
     if ((int64_t)(s.P[2] / 2) * zrow_bytes > (int64_t)INT32_MAX)
         fail(DDSTRESS_E_UNSUPPORTED, "grid too large for the z pass's 32-bit plane offsets: Pz/2 * Py * Wx complex "
@@ -372,6 +373,70 @@ void upload_twiddles(ddstress_plan_s* p, hipStream_t st) {
 // several times in a row recomputes the same output.
 // Plane statistics targets of one call: per-row sums of squares and the
 // per-plane results (both NULL: no statistics).
+// Layout of the spectrum buffers between the y passes and the fused z pass,
+// per group (realisation and channel, or realisation and stress component).
+// Plane-major, [group][z][ky][kx]: each (group, z) plane contiguous, Py rows
+// of wx complex values. Ky-major, [group][ky][z][kx]: the Nz z-rows of each
+// ky together, so a z column's rows lie wx values apart and the fused z pass
+// reads and writes neighbouring 128-byte pieces rather than one piece per
+// plane; a (group, z) plane then has its rows Nz wx apart. The fused x-y
+// kernels, which walk the planes of a group one after the other, take the
+// ky-major layout at no cost (interleave Nz); the separate column passes,
+// whose blocks own one plane's columns, keep their rows together in the
+// plane-major layout. Each buffer takes the layout of its y pass.
+// Forward y (separate pass): x-pass output [group][z][y][kx] -> plane-major.
+ColGeom fwd_y_geom(const Shape& s, int64_t groups) {
+    const int Ny = s.N[1], Nz = s.N[2], Py = s.P[1];
+    ColGeom g{};
+    g.ncols = s.M1;
+    g.n_in = Ny;
+    g.n_out = Py;
+    g.nouter = 1;
+    g.nplanes = groups * Nz;
+    g.irs = s.wx;
+    g.ips = (int64_t)Ny * s.wx;
+    g.ors = s.wx;
+    g.ops = (int64_t)Py * s.wx;
+    return g;
+}
+// Inverse y (separate pass): plane-major -> [group][z][y][kx] (Ny rows).
+ColGeom inv_y_geom(const Shape& s, int64_t groups) {
+    const int Ny = s.N[1], Nz = s.N[2], Py = s.P[1];
+    ColGeom g{};
+    g.ncols = s.M1;
+    g.n_in = Py;
+    g.n_out = Ny;
+    g.nouter = 1;
+    g.nplanes = groups * Nz;
+    g.irs = s.wx;
+    g.ips = (int64_t)Py * s.wx;
+    g.ors = s.wx;
+    g.ops = (int64_t)Ny * s.wx;
+    return g;
+}
+// Fused z pass: the density buffer ky-major when kin, the stress buffer when kout.
+ZGeom z_geom(const Shape& s, int tk, int nb, bool kin, bool kout) {
+    const int Nz = s.N[2], Py = s.P[1];
+    ZGeom g{};
+    g.nky_s = s.nkys;
+    g.nkz_s = s.nkzs;
+    g.sgn_y = s.sgn_y;
+    g.sgn_z = s.sgn_z;
+    g.ncols = s.M1;
+    g.ntiles = (s.M1 + tk - 1) / tk;
+    g.nky = Py;
+    g.nz = Nz;
+    g.C = s.C;
+    g.B = nb;
+    g.irs = kin ? s.wx : (int64_t)Py * s.wx;             // z rows
+    g.ios = kin ? (int64_t)Nz * s.wx : s.wx;             // ky rows
+    g.iqs = (int64_t)Nz * Py * s.wx;
+    g.ors = kout ? s.wx : (int64_t)Py * s.wx;
+    g.oos = kout ? (int64_t)Nz * s.wx : s.wx;
+    g.oqs = g.iqs;
+    return g;
+}
+
 struct StatsTarget {
     double* rowsq;
     double* stats;
@@ -394,7 +459,7 @@ void enqueue_pass(ddstress_plan_s* p, int k, const T* rho, T* sigma, int nb, hip
     if (k == 0) {
         if constexpr (sizeof(T) == 4) {
             if (xy) {
-                launch_xy_fwd(rho, w2, BC * Nz, Py, s.M, Ny, Nx, s.wx, tw, st);
+                launch_xy_fwd(rho, w2, BC * Nz, Py, s.M, Ny, Nx, s.wx, tw, st, Nz);   // ky-major
                 return;
             }
         }
@@ -403,37 +468,11 @@ void enqueue_pass(ddstress_plan_s* p, int k, const T* rho, T* sigma, int nb, hip
     } else if (k == 1) {
         if (xy) return;
         // y forward: Ny rows -> Py rows
-        ColGeom gy{};
-        gy.ncols = s.M1;
-        gy.n_in = Ny;
-        gy.n_out = Py;
-        gy.nouter = 1;
-        gy.nplanes = BC * Nz;
-        gy.irs = s.wx;
-        gy.ips = (int64_t)Ny * s.wx;
-        gy.ors = s.wx;
-        gy.ops = (int64_t)Py * s.wx;
-        launch_col_fft<T>(Py, p->ey, true, w1, w2, gy, tw, p->tk_y, st);
+        launch_col_fft<T>(Py, p->ey, true, w1, w2, fwd_y_geom(s, BC), tw, p->tk_y, st);
     } else if (k == 2) {
         // z forward + contraction + z inverse
-        ZGeom gz{};
-        gz.nky_s = s.nkys;
-        gz.nkz_s = s.nkzs;
-        gz.sgn_y = s.sgn_y;
-        gz.sgn_z = s.sgn_z;
-        gz.ncols = s.M1;
-        gz.ntiles = s.ntz;
-        gz.nky = Py;
-        gz.nz = Nz;
-        gz.C = s.C;
-        gz.B = s.B;
-        gz.irs = (int64_t)Py * s.wx;
-        gz.iqs = (int64_t)Nz * Py * s.wx;
-        gz.ios = s.wx;
-        gz.ors = gz.irs;
-        gz.oqs = gz.iqs;
-        gz.oos = gz.ios;
-        launch_z_fused<T>(s.P[2], p->ez, s.zg, w2, w1, p->spec->as<T>(), gz, tw, s.tkz, st);
+        launch_z_fused<T>(s.P[2], p->ez, s.zg, w2, w1, p->spec->as<T>(), z_geom(s, s.tkz, s.B, xy, yx), tw, s.tkz,
+                          st);
     } else if (k == 3 || k == 4) {
         // plane statistics (Eq. 20) from per-row sums of the inverse x pass
         double* rowsq = stt.stats ? stt.rowsq : nullptr;
@@ -442,23 +481,13 @@ void enqueue_pass(ddstress_plan_s* p, int k, const T* rho, T* sigma, int nb, hip
         if (k == 3) {
             if constexpr (sizeof(T) == 4) {
                 if (yx) {
-                    launch_yx_inv(w1, sigma, B6 * Nz, Py, s.M, Ny, Nx, s.wx, tw, st, rowsq);
+                    launch_yx_inv(w1, sigma, B6 * Nz, Py, s.M, Ny, Nx, s.wx, tw, st, rowsq, Nz);   // ky-major
                     if (rowsq) launch_rowsq_finish(rowsq, B6 * Nz, Ny, inv_plane, stats_out, st);
                     return;
                 }
             }
             // y inverse: Py rows -> Ny rows
-            ColGeom gi{};
-            gi.ncols = s.M1;
-            gi.n_in = Py;
-            gi.n_out = Ny;
-            gi.nouter = 1;
-            gi.nplanes = B6 * Nz;
-            gi.irs = s.wx;
-            gi.ips = (int64_t)Py * s.wx;
-            gi.ors = s.wx;
-            gi.ops = (int64_t)Ny * s.wx;
-            launch_col_fft<T>(Py, p->ey, false, w1, w2, gi, tw, p->tk_y, st);
+            launch_col_fft<T>(Py, p->ey, false, w1, w2, inv_y_geom(s, B6), tw, p->tk_y, st);
         } else {
             if (yx) return;
             // x inverse: rows (b, v, z, y) -> Nx reals
@@ -733,12 +762,8 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
     for (int ev : {8, 16})
         for (int tk = 1; tk <= 256; tk *= 2) {
             if (!col_ok(s, Py, tk, ev) || col_threads(Py, tk, ev) < 64 || (ev == 16 && Py <= 8)) continue;
-            ColGeom gy{};
-            gy.ncols = s.M1; gy.n_in = Ny; gy.n_out = Py; gy.nouter = 1; gy.nplanes = BC * Nz;
-            gy.irs = s.wx; gy.ips = (int64_t)Ny * s.wx; gy.ors = s.wx; gy.ops = (int64_t)Py * s.wx;
-            ColGeom gi{};
-            gi.ncols = s.M1; gi.n_in = Py; gi.n_out = Ny; gi.nouter = 1; gi.nplanes = B6 * Nz;
-            gi.irs = s.wx; gi.ips = (int64_t)Py * s.wx; gi.ors = s.wx; gi.ops = (int64_t)Ny * s.wx;
+            const ColGeom gy = fwd_y_geom(s, BC);
+            const ColGeom gi = inv_y_geom(s, B6);
             float ms = time_median(st, reps, [&] {
                 launch_col_fft<T>(Py, ev, true, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gy, twp, tk, st);
                 launch_col_fft<T>(Py, ev, false, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gi, twp, tk, st);
@@ -749,11 +774,9 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
     best = 1e30f;
     for (auto& z : zlist) {
         const int tk = z.tk, ev = z.ev, groups = z.groups;
-        ZGeom gz{};
-        gz.nky_s = s.nkys; gz.nkz_s = s.nkzs;
-        gz.ncols = s.M1; gz.ntiles = (s.M1 + tk - 1) / tk; gz.nky = Py; gz.nz = Nz; gz.C = s.C; gz.B = s.B;
-        gz.irs = (int64_t)Py * s.wx; gz.iqs = (int64_t)Nz * Py * s.wx; gz.ios = s.wx;
-        gz.ors = gz.irs; gz.oqs = gz.iqs; gz.oos = gz.ios;
+        // the layouts of fused x-y passes where they apply (they are chosen below)
+        ZGeom gz = z_geom(s, tk, s.B, sizeof(T) == 4 && yx_ok(s), sizeof(T) == 4 && yx_ok(s));
+        gz.sgn_y = gz.sgn_z = 0;                 // (the tuning spectrum is zeros)
         float ms = time_median(st, reps, [&] {
             launch_z_fused<T>(Pz, ev, groups, w2.as<cplx<T>>(), w1.as<cplx<T>>(), spec.as<T>(), gz, twp, tk, st);
         });
@@ -771,29 +794,26 @@ void autotune_impl(const ddstress_desc* desc, hipStream_t st, ddstress_tuning* o
     out->xy = 1;
     if constexpr (sizeof(T) == 4) {
         if (yx_ok(s)) {
-            ColGeom gi{};
-            gi.ncols = s.M1; gi.n_in = Py; gi.n_out = Ny; gi.nouter = 1; gi.nplanes = B6 * Nz;
-            gi.irs = s.wx; gi.ips = (int64_t)Py * s.wx; gi.ors = s.wx; gi.ops = (int64_t)Ny * s.wx;
+            const ColGeom gi = inv_y_geom(s, B6);
             const float sep = time_median(st, reps, [&] {
                 launch_col_fft<T>(Py, out->ey, false, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gi, twp, out->tk_y, st);
                 launch_x_c2r<T>(s.M, out->ex, w2.as<cplx<T>>(), sig.as<T>(), B6 * Nz * Ny, Nx, s.wx, Nx, twp,
                                 out->rows_x, st);
             });
             const float fused = time_median(st, reps, [&] {
-                launch_yx_inv(w1.as<cplx<float>>(), sig.as<float>(), B6 * Nz, Py, s.M, Ny, Nx, s.wx, twp, st);
+                launch_yx_inv(w1.as<cplx<float>>(), sig.as<float>(), B6 * Nz, Py, s.M, Ny, Nx, s.wx, twp, st,
+                              nullptr, Nz);
             });
             if (verbose) std::fprintf(stderr, "[tune] inverse y+x separate %.5f ms fused %.5f ms\n", sep, fused);
             if (fused < sep) out->yx = 2;
-            ColGeom gy{};
-            gy.ncols = s.M1; gy.n_in = Ny; gy.n_out = Py; gy.nouter = 1; gy.nplanes = BC * Nz;
-            gy.irs = s.wx; gy.ips = (int64_t)Ny * s.wx; gy.ors = s.wx; gy.ops = (int64_t)Py * s.wx;
+            const ColGeom gy = fwd_y_geom(s, BC);
             const float sepf = time_median(st, reps, [&] {
                 launch_x_r2c<T>(s.M, out->ex, rho.as<T>(), w1.as<cplx<T>>(), BC * Nz * Ny, Nx, Nx, s.wx, twp,
                                 out->rows_x, st);
                 launch_col_fft<T>(Py, out->ey, true, w1.as<cplx<T>>(), w2.as<cplx<T>>(), gy, twp, out->tk_y, st);
             });
             const float fusedf = time_median(st, reps, [&] {
-                launch_xy_fwd(rho.as<float>(), w2.as<cplx<float>>(), BC * Nz, Py, s.M, Ny, Nx, s.wx, twp, st);
+                launch_xy_fwd(rho.as<float>(), w2.as<cplx<float>>(), BC * Nz, Py, s.M, Ny, Nx, s.wx, twp, st, Nz);
             });
             if (verbose) std::fprintf(stderr, "[tune] forward x+y separate %.5f ms fused %.5f ms\n", sepf, fusedf);
             out->xy = fusedf < sepf ? 2 : 1;

@@ -157,7 +157,21 @@ struct ZGeom {
     int C, B;              // channels and batch
     int64_t irs, iqs, ios; // input z / plane / ky strides
     int64_t ors, oqs, oos; // output strides (6B planes)
+    int nyq;               // groups of the Nyquist strip (z_nyq_groups; set by launch_z_fused)
 };
+
+// Nyquist strip of the fused z pass. When the last kx tile would hold the
+// column kx = M (= ncols - 1) alone, which happens whenever M is a multiple of
+// the tile width tk, that tile's blocks hold the column at tk consecutive ky
+// instead: group q covers ky = q tk .. q tk + tk - 1, and only ky <= Py/2 is
+// evaluated (the column is Hermitian along y; the rest is written as the
+// conjugate mirror); one block per group and realisation. The spectrum keeps
+// the strip in the last tile's slot, group q at row q, lane c at column c.
+// Returns the number of groups, or 0 when the last tile holds other columns
+// too.
+__host__ __device__ inline int z_nyq_groups(int ncols, int tk, int nky) {
+    return (ncols > tk && (ncols - 1) % tk == 0) ? (nky / 2 + tk) / tk : 0;
+}
 template <typename T>
 void launch_z_fused(int N, int ev, int groups, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
                     const cplx<T>* tw, int tk, hipStream_t s);
@@ -198,12 +212,15 @@ void z_dispatch(int N, int ev, const cplx<T>* in, cplx<T>* out, const T* spec, c
                 const cplx<T>* tw, int tk, int64_t blocks, hipStream_t s);
 
 // Fused forward x and y, and fused inverse y and x, for planes that fit one
-// block's LDS (yx_fused.hip): FP32, Py = 256, M = 128.
+// block's LDS (yx_fused.hip): FP32, Py = 256, M = 128. The spectrum planes
+// (Py rows of wx complex values) are interleaved in groups of zp: plane p
+// starts at (p / zp) zp Py wx + (p % zp) wx and its rows are zp wx apart
+// (zp = 1: each plane contiguous).
 bool yx_inv_fits(int Py, int M, int ny, int elem_bytes);
 void launch_yx_inv(const cplx<float>* in, float* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
-                   const cplx<float>* tw, hipStream_t s, double* rowsq = nullptr);
+                   const cplx<float>* tw, hipStream_t s, double* rowsq = nullptr, int zp = 1);
 void launch_xy_fwd(const float* in, cplx<float>* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
-                   const cplx<float>* tw, hipStream_t s);
+                   const cplx<float>* tw, hipStream_t s, int zp = 1);
 
 // Every power-of-two transform length the passes support.
 #define DDS_FOR_LENGTHS(X, EV) X(1, EV) X(2, EV) X(4, EV) X(8, EV) X(16, EV) X(32, EV) X(64, EV) \

@@ -188,6 +188,25 @@ __device__ __forceinline__ cplx<double> buf_cplx<double>(__amdgpu_buffer_rsrc_t 
     return {__hiloint2double((int)v[1], (int)v[0]), __hiloint2double((int)v[3], (int)v[2])};
 }
 
+// Raw buffer store of one complex value: dropped by the hardware when the
+// byte offset lies at or beyond the resource's size.
+template <typename T>
+__device__ __forceinline__ void buf_store_cplx(__amdgpu_buffer_rsrc_t r, int voff, int soff, cplx<T> v);
+template <>
+__device__ __forceinline__ void buf_store_cplx<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff, cplx<float> v) {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 d = {__float_as_uint(v.x), __float_as_uint(v.y)};
+    __builtin_amdgcn_raw_buffer_store_b64(d, r, voff, soff, 0);
+}
+template <>
+__device__ __forceinline__ void buf_store_cplx<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff, cplx<double> v) {
+    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+    const unsigned long long a = (unsigned long long)__double_as_longlong(v.x);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v.y);
+    const u4 d = {(unsigned)a, (unsigned)(a >> 32), (unsigned)b, (unsigned)(b >> 32)};
+    __builtin_amdgcn_raw_buffer_store_b128(d, r, voff, soff, 0);
+}
+
 // The hardware hands consecutive workgroups of a launch to the eight XCDs in
 // turn, and each XCD has its own L2. Logical block index of workgroup b of nb
 // such that every XCD works through one contiguous range of logical blocks

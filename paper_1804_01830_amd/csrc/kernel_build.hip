@@ -219,9 +219,11 @@ __global__ void __launch_bounds__(256) k_mirror_stats(const double* __restrict__
 
 // Spectrum extraction: S = Im(K^) / P for the channels 3*line .. 3*line+2,
 // stored as [kyc][tile][c][v][kzc][tk] for kyc < nky, kzc < nkz (the kept
-// halves when a mirror symmetry lets the rest be reconstructed). One thread
-// per (kx in the tiled range, kyc, kzc), looping over the 18 planes; also the
-// maxima of |Re K^| and |Im K^| over the kept entries.
+// halves when a mirror symmetry lets the rest be reconstructed). With a
+// Nyquist strip (z_nyq_groups) the last tile's slot at row q holds instead
+// the column kx = M at ky = q tk + col, for ky <= Py/2 (zeros elsewhere). One
+// thread per (kx in the tiled range, kyc, kzc), looping over the 18 planes;
+// also the maxima of |Re K^| and |Im K^| over the kept entries.
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract(const cplx<double>* __restrict__ kh, T* __restrict__ spec,
                                                  int line, int C, int ncols, int64_t wx, int Py, int Pz, int nky,
@@ -234,12 +236,16 @@ __global__ void __launch_bounds__(256) k_extract(const cplx<double>* __restrict_
     double re = 0.0, im = 0.0;
     if (kx < kxr) {
         const int tile = kx / tk, col = kx % tk;
+        const bool strip = tile == ntiles - 1 && z_nyq_groups(ncols, tk, Py) > 0;
+        const int sx = strip ? ncols - 1 : kx;                  // source column and row
+        const int sy = strip ? ky * tk + col : ky;
+        const bool have = strip ? 2 * sy <= Py : kx < ncols;
         for (int gv = 0; gv < 18; ++gv) {
             const int g = gv / 6, v = gv % 6;
             const int ch = 3 * line + g;
             const int64_t o = (((((int64_t)ky * ntiles + tile) * C + ch) * 6 + v) * nkz + kz) * tk + col;
-            if (kx < ncols) {
-                const cplx<double> val = kh[(((int64_t)gv * Pz + kz) * Py + ky) * wx + kx];
+            if (have) {
+                const cplx<double> val = kh[(((int64_t)gv * Pz + kz) * Py + sy) * wx + sx];
                 re = fmax(re, fabs(val.x));
                 im = fmax(im, fabs(val.y));
                 spec[o] = (T)(val.y * inv_p);

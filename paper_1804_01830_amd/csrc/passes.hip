@@ -504,9 +504,15 @@ void launch_col_fft(int N, int ev, bool forward, const cplx<T>* in, cplx<T>* out
 }
 
 template <typename T>
-void launch_z_fused(int N, int ev, int groups, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& g,
+void launch_z_fused(int N, int ev, int groups, const cplx<T>* in, cplx<T>* out, const T* spec, const ZGeom& geom,
                     const cplx<T>* tw, int tk, hipStream_t s) {
-    const int64_t blocks = (int64_t)g.ntiles * g.nky;
+    if (tk < 1 || geom.ntiles != (geom.ncols + tk - 1) / tk)
+        fail(DDSTRESS_E_INVALID, "fused z tiles do not match the tile width");
+    ZGeom g = geom;
+    g.nyq = z_nyq_groups(g.ncols, tk, g.nky);
+    // tiles x ky rows; in place of the Nyquist strip's tile, its groups x realisations
+    const int64_t blocks = g.nyq > 0 ? (int64_t)(g.ntiles - 1) * g.nky + (int64_t)g.nyq * g.B
+                                     : (int64_t)g.ntiles * g.nky;
     if (blocks <= 0) return;
     if (blocks > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
     if (!ev_z_ok(N, ev, (int)sizeof(T))) fail(DDSTRESS_E_INVALID, "z element class not supported for this length");

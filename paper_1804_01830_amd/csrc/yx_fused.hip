@@ -71,7 +71,7 @@ template <int PY, int M>
 __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __restrict__ in, float* __restrict__ out,
                                                        int64_t nplanes, int ny, int nx, int64_t wx,
                                                        const cplx<float>* __restrict__ tw, int xld, int xsh,
-                                                       int pairs, double* __restrict__ rowsq) {
+                                                       int pairs, double* __restrict__ rowsq, int zp) {
     using T = float;
     constexpr int PLD = PY / 2;                          // plane column stride: rows y < Py/2
     constexpr int GC = 16, EY = 8, TCY = PY / EY;        // y: 16 columns per group, Tc threads per column
@@ -101,10 +101,11 @@ __global__ void __launch_bounds__(kYXThreads) k_yx_inv(const cplx<float>* __rest
         yx_round<PY, M, GC, GT>(c0, groups, ncols);
         const int c = c0 + gi * GC + cl;
         const bool valid = gi < groups && c < M;
-        const cplx<T>* src = in + pl * (int64_t)PY * wx;
+        const cplx<T>* src = in + (pl / zp) * zp * (int64_t)PY * wx + (pl % zp) * wx;   // interleaved planes
+        const int64_t rs = (int64_t)zp * wx;
 #pragma unroll
         for (int m = 0; m < EY; ++m) {
-            const int64_t r = (int64_t)(jy + TCY * m) * wx;
+            const int64_t r = (int64_t)(jy + TCY * m) * rs;
             nxt[m] = valid ? src[r + c] : cplx<T>{T(0), T(0)};
             if (valid && c == 0) {
                 const cplx<T> xm = src[r + M];
@@ -208,7 +209,7 @@ template <int PY, int M, bool HX>
 __global__ void __launch_bounds__(kYXThreads) k_xy_fwd(const float* __restrict__ in, cplx<float>* __restrict__ out,
                                                        int64_t nplanes, int ny, int nx, int64_t wx,
                                                        const cplx<float>* __restrict__ tw, int xld, int xsh,
-                                                       int pairs) {
+                                                       int pairs, int zp) {
     using T = float;
     constexpr int M1 = M + 1;
     constexpr int PLD = PY / 2;
@@ -315,7 +316,8 @@ __global__ void __launch_bounds__(kYXThreads) k_xy_fwd(const float* __restrict__
         //    once per plane, before the next plane's rows are requested: vector
         //    loads (and stores) complete in issue order, so a twiddle load issued
         //    after the rows or a round's stores would wait for them.
-        cplx<T>* dst = out + plane * (int64_t)PY * wx;
+        cplx<T>* dst = out + (plane / zp) * zp * (int64_t)PY * wx + (plane % zp) * wx;   // interleaved planes
+        const int64_t rs = (int64_t)zp * wx;
         const int gi = tt / GT, cl = (tt % GT) % GC;
         int jy = (tt % GT) / GC;
         cplx<T> twy[TWY];
@@ -345,7 +347,7 @@ __global__ void __launch_bounds__(kYXThreads) k_xy_fwd(const float* __restrict__
             fft_regs_k<T, PY, EY, true, true, 1, TWY>(col, twy, scratch, 0, ColMajor{GC}, cl, jy, act);
             if (valid) {
 #pragma unroll
-                for (int m = 0; m < EY; ++m) dst[(int64_t)(jy + TCY * m) * wx + c] = col[0][m];
+                for (int m = 0; m < EY; ++m) dst[(int64_t)(jy + TCY * m) * rs + c] = col[0][m];
             }
             c0 += ncols;
         }
@@ -363,12 +365,13 @@ bool yx_inv_fits(int Py, int M, int ny, int elem_bytes) {
 }
 
 void launch_xy_fwd(const float* in, cplx<float>* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
-                   const cplx<float>* tw, hipStream_t s) {
+                   const cplx<float>* tw, hipStream_t s, int zp) {
     if (nplanes <= 0) return;
     if (!yx_inv_fits(Py, M, ny, 4)) fail(DDSTRESS_E_INVALID, "plane does not fit the fused forward x-y kernel");
     if ((size_t)(Py / 2) * x_lds_layout(M, 16, 4).ld + 2 * (size_t)M > (size_t)kYXLds / sizeof(cplx<float>))
         fail(DDSTRESS_E_INVALID, "row exchanges and twiddle tables exceed the fused forward kernel's LDS");
     if (nplanes > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
+    if (zp < 1 || nplanes % zp != 0) fail(DDSTRESS_E_INVALID, "plane interleave must divide the plane count");
     const XLayout xl = x_lds_layout(M, 16, 4);
     const int pairs = (reinterpret_cast<uintptr_t>(in) % 8 == 0 && nx % 2 == 0) ? 1 : 0;
     // one resident block per CU walks over the planes; rows of nx <= M reals
@@ -376,26 +379,27 @@ void launch_xy_fwd(const float* in, cplx<float>* out, int64_t nplanes, int Py, i
     const int64_t grid = nplanes < kYXBlocks ? nplanes : kYXBlocks;
     if (nx <= M)
         hipLaunchKernelGGL((k_xy_fwd<256, 128, true>), dim3((unsigned)grid), dim3(kYXThreads), kYXLds, s, in, out,
-                           nplanes, ny, nx, wx, tw, xl.ld, xl.s, pairs);
+                           nplanes, ny, nx, wx, tw, xl.ld, xl.s, pairs, zp);
     else
         hipLaunchKernelGGL((k_xy_fwd<256, 128, false>), dim3((unsigned)grid), dim3(kYXThreads), kYXLds, s, in, out,
-                           nplanes, ny, nx, wx, tw, xl.ld, xl.s, pairs);
+                           nplanes, ny, nx, wx, tw, xl.ld, xl.s, pairs, zp);
     check_hip(hipGetLastError(), "fused forward x-y launch");
 }
 
 void launch_yx_inv(const cplx<float>* in, float* out, int64_t nplanes, int Py, int M, int ny, int nx, int64_t wx,
-                   const cplx<float>* tw, hipStream_t s, double* rowsq) {
+                   const cplx<float>* tw, hipStream_t s, double* rowsq, int zp) {
     if (nplanes <= 0) return;
     if (!yx_inv_fits(Py, M, ny, 4)) fail(DDSTRESS_E_INVALID, "plane does not fit the fused inverse y-x kernel");
     if ((size_t)(Py / 2) * x_lds_layout(M, 16, 4).ld + 2 * (size_t)M > (size_t)kYXLds / sizeof(cplx<float>))
         fail(DDSTRESS_E_INVALID, "row exchanges and twiddle tables exceed the fused inverse kernel's LDS");
     if (nplanes > 0x7fffffffLL) fail(DDSTRESS_E_UNSUPPORTED, "grid too large for one launch");
+    if (zp < 1 || nplanes % zp != 0) fail(DDSTRESS_E_INVALID, "plane interleave must divide the plane count");
     const XLayout xl = x_lds_layout(M, 16, 4);
     const int pairs = (reinterpret_cast<uintptr_t>(out) % 8 == 0 && nx % 2 == 0) ? 1 : 0;
     // one resident block per CU walks over the planes
     const int64_t grid = nplanes < kYXBlocks ? nplanes : kYXBlocks;
     hipLaunchKernelGGL((k_yx_inv<256, 128>), dim3((unsigned)grid), dim3(kYXThreads), kYXLds, s, in, out, nplanes, ny,
-                       nx, wx, tw, xl.ld, xl.s, pairs, rowsq);
+                       nx, wx, tw, xl.ld, xl.s, pairs, rowsq, zp);
     check_hip(hipGetLastError(), "fused inverse y-x launch");
 }
 

@@ -48,18 +48,117 @@ __device__ __forceinline__ NyquistRole nyquist_role(int tile, int tk, int col, i
     return {tile * tk == m && upper, valid && !(nyq && upper), nyq && ky > 0 && 2 * ky < g.nky};
 }
 
+// Roles of a block of the fused z pass and of its lane in column slot c of
+// the tile: the spectrum tile and stored row it reads, the element offsets of
+// its input and output columns, and its realisations [b0, b1). With a Nyquist
+// strip (g.nyq groups, see z_nyq_groups) the last tile is the strip, whose
+// blocks hold the column kx = M at ky = q tk + c for group q. A strip lane
+// reads and writes its own row (one cache line per value, against one per
+// tk values elsewhere), so each strip block takes one realisation: blocks
+// q B + b come first, short, and never form the launch's tail. The following
+// blocks take the other kx tiles by z_block_coords and every realisation.
+//
+// Logical block of this workgroup: the strip's blocks are the first
+// workgroups, which the hardware deals to the eight XCDs in turn (so each
+// XCD gets its share of them); the others go through xcd_block, which gives
+// every XCD a contiguous range of the remaining tiles.
+__device__ __forceinline__ int z_logical_block(const ZGeom& g) {
+    const int b = (int)blockIdx.x, strip = g.nyq * g.B;
+    return b < strip ? b : strip + xcd_block(b - strip, (int)gridDim.x - strip);
+}
+struct ZRoles {
+    int tile, kyc;        // spectrum tile and stored row
+    bool flip_y;          // row kyc is the y mirror of the block's ky (odd planes change sign)
+    int64_t in0;          // offset of the block's first input column in a density plane
+    int lane_in;          // offset of this lane's column from in0 (lanes without data: 0, a valid column)
+    int64_t own, mir;     // offsets of this lane's output column at its ky and at Py - ky
+    int64_t own0;         // the block's first own output column (own = own0 + lane_out)
+    int lane_out;
+    uint32_t in_bytes;    // bytes from in0, and from own0, to the end of a density / stress plane
+    uint32_t out_bytes;
+    int b0, b1;           // realisations of the block
+    NyquistRole nq;
+};
+template <typename T>
+__device__ __forceinline__ ZRoles z_roles(int blk, int tk, int c, const ZGeom& g) {
+    ZRoles r;
+    const int tiles = g.nyq > 0 ? g.ntiles - 1 : g.ntiles;
+    const int strip_blocks = g.nyq * g.B;
+    if (blk < strip_blocks) {                    // the Nyquist strip
+        const int q = blk / g.B, m = g.ncols - 1;
+        r.b0 = blk - q * g.B;
+        r.b1 = r.b0 + 1;
+        const int ky = q * tk + c;
+        const bool valid = 2 * ky <= g.nky;
+        const int kyv = valid ? ky : q * tk;
+        r.tile = g.ntiles - 1;
+        r.kyc = q;
+        r.flip_y = false;
+        r.in0 = (int64_t)q * tk * g.ios + m;
+        r.lane_in = valid ? c * (int)g.ios : 0;
+        r.own = (int64_t)kyv * g.oos + m;
+        r.mir = (int64_t)(g.nky - kyv) * g.oos + m;
+        r.own0 = (int64_t)q * tk * g.oos + m;
+        r.lane_out = (kyv - q * tk) * (int)g.oos;
+        r.in_bytes = (uint32_t)((g.iqs - r.in0) * (int64_t)sizeof(cplx<T>));
+        r.out_bytes = (uint32_t)((g.oqs - r.own0) * (int64_t)sizeof(cplx<T>));
+        r.nq = {false, valid, valid && ky > 0 && 2 * ky < g.nky};
+        return r;
+    }
+    int tile, ky;
+    z_block_coords(blk - strip_blocks, tiles, g.nky, tile, ky);
+    const int col = tile * tk + c;
+    const bool valid = col < g.ncols;
+    const int colc = valid ? col : 0;
+    r.b0 = 0;
+    r.b1 = g.B;
+    r.tile = tile;
+    r.flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
+    r.kyc = r.flip_y ? g.nky - ky : ky;
+    r.in0 = (int64_t)ky * g.ios + (int64_t)tile * tk;
+    r.lane_in = valid ? c : 0;
+    r.own = (int64_t)ky * g.oos + colc;
+    r.mir = (int64_t)(g.nky - ky) * g.oos + colc;
+    r.own0 = (int64_t)ky * g.oos + (int64_t)tile * tk;
+    r.lane_out = valid ? c : 0;
+    r.in_bytes = (uint32_t)((g.iqs - r.in0) * (int64_t)sizeof(cplx<T>));
+    r.out_bytes = (uint32_t)((g.oqs - r.own0) * (int64_t)sizeof(cplx<T>));
+    r.nq = nyquist_role(tile, tk, col, ky, valid, g);
+    return r;
+}
+
+// Byte offsets of a lane's rows z = j + Tc m (m < EH) at row stride rs from
+// its block's base, the lane's column at `lane` elements: rows z >= nz, and
+// every row when `on` is false, take the resource's size `end` as offset, so
+// their loads read zero and their stores are dropped (the row part Tc m rs
+// is added as the wave-uniform offset, which keeps them beyond it).
+template <typename T, int EH>
+__device__ __forceinline__ void row_offsets(int (&off)[EH], bool on, int j, int Tc, int lane, int rs, int nz,
+                                            uint32_t end) {
+#pragma unroll
+    for (int m = 0; m < EH; ++m)
+        off[m] = (on && j + Tc * m < nz) ? (j * rs + lane) * (int)sizeof(cplx<T>) : (int)end;
+}
+
+// Sign flip of x when the (wave-uniform) mask holds the sign bit: one integer
+// operation in place of a select and a product with -1 (the same bits).
+__device__ __forceinline__ float flip_sign(float x, uint32_t msk) { return __uint_as_float(__float_as_uint(x) ^ msk); }
+__device__ __forceinline__ double flip_sign(double x, uint32_t msk) {
+    return __longlong_as_double(__double_as_longlong(x) ^ (long long)((uint64_t)msk << 32));
+}
+__device__ __forceinline__ uint32_t sign_mask(bool neg) { return neg ? 0x80000000u : 0u; }
+
 // Copy a block's spectrum tile [c][v][kz][TK] (nkz rows kz, NC channels,
 // six components) into LDS as rows kz of [c][v][TK] values with the row
 // stride (6 NC + 1) TK, applying the y-mirror sign of the odd planes (bit
 // c 6 + v of sgn_y) when flip_y. NT threads (tid < NT) copy 16-byte pieces,
-// up to 16 loads each in flight before their stores; a piece never straddles
+// up to CH loads each in flight before their stores; a piece never straddles
 // a source row (TK is a multiple of its width). The caller synchronises.
-template <typename T, int NC, int TK, int NT>
+template <typename T, int NC, int TK, int NT, int CH = 16>
 __device__ __forceinline__ void stage_spectrum_tile(T* s_l, __amdgpu_buffer_rsrc_t srs, int nkz, bool flip_y,
                                                     uint64_t sgn_y, int tid) {
     constexpr int KS = (6 * NC + 1) * TK;
     constexpr int VW = 16 / (int)sizeof(T);
-    constexpr int CH = 16;
     const int n_vals = NC * 6 * nkz * TK;
     const float rcp = 1.0f / (float)nkz;
     for (int k0 = 0; k0 * NT * VW < n_vals; k0 += CH) {
@@ -94,7 +193,8 @@ __device__ __forceinline__ void stage_spectrum_tile(T* s_l, __amdgpu_buffer_rsrc
 
 // ----------------------------------------------------------------------------
 // Fused z pass, single-group form. A block owns `tk` consecutive kx columns at
-// one ky and one group of Tc * tk threads. For every realisation b it
+// one ky (in the Nyquist strip: the column kx = M at tk consecutive ky, see
+// z_roles) and one group of Tc * tk threads. For every realisation b it
 // transforms the C density columns along z one after the other (rows
 // z >= N/2 are the zero padding and are not loaded), accumulates the six
 // stress spectra
@@ -128,45 +228,44 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
     cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
     const int c = threadIdx.x % tk;
     const int j = threadIdx.x / tk;
-    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    int tile, ky;
-    z_block_coords(blk, g.ntiles, g.nky, tile, ky);
-    const int col = tile * tk + c;
-    const bool valid = col < g.ncols;
-    const int colc = valid ? col : 0;
+    const int blk = z_logical_block(g);
+    const ZRoles ro = z_roles<T>(blk, tk, c, g);
+    const NyquistRole nq = ro.nq;
+    if (nq.skip_block) return;                   // uniform over the block, before any barrier
     const ColMajor lay{ld};
     const int ors = (int)g.ors;
     // Spectrum tile of this block: [c][v][kzc][tk] at row kyc. With a y mirror
     // only ky <= Py/2 is stored and row Py - ky stands in for ky > Py/2; with
     // a z mirror only kz <= N/2 is stored and elements m >= E/2 read
     // kz' = N - kz = (Tc - j) + Tc (E - 1 - m). Odd planes change sign.
-    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
-    const int kyc = flip_y ? g.nky - ky : ky;
+    const bool flip_y = ro.flip_y;
     const bool zc = g.nkz_s < N;
     const int nkz = g.nkz_s;
-    const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * tk;
+    const T* sp = spec + ((int64_t)ro.kyc * g.ntiles + ro.tile) * (int64_t)g.C * 6 * nkz * tk;
     const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * tk * sizeof(T)));
     const int s_lane = (j * tk + c) * (int)sizeof(T);
     const int s_lane_m = ((Tc - j) * tk + c) * (int)sizeof(T);
-    // density rows z < nz of the block's columns; rows >= nz lie beyond the
-    // resource and read as zero. Lanes of padding columns (col >= ncols) read
-    // the tile's first column, which is valid.
-    const cplx<T>* in_b = in + (int64_t)ky * g.ios + (int64_t)tile * tk;
-    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
-    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
+    // density rows z < nz of the block's columns (rows >= nz read zero; lanes
+    // without data read a valid column)
+    const cplx<T>* in_b = in + ro.in0;
+    int r_off[EH];
+    row_offsets<T, EH>(r_off, true, j, Tc, ro.lane_in, (int)g.irs, g.nz, ro.in_bytes);
     const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
-    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
-    const NyquistRole nq = nyquist_role(tile, tk, col, ky, valid, g);
-    if (nq.skip_block) return;                   // uniform over the block, before any barrier
-    cplx<T>* mir_b = out + (int64_t)(g.nky - ky) * g.oos + colc;
+    cplx<T>* mir_b = out + ro.mir;
+    // own stores: rows z < nz of the lane's output column (lanes without an
+    // own column store nothing)
+    const cplx<T>* out_b = out + ro.own0;
+    int o_off[EH];
+    row_offsets<T, EH>(o_off, nq.own, j, Tc, ro.lane_out, ors, g.nz, ro.out_bytes);
+    const int o_step = Tc * ors * (int)sizeof(cplx<T>);
 
 #define DDS_LOAD_RHO(DST, BB, CH)                                                          \
     {                                                                                      \
-        const __amdgpu_buffer_rsrc_t rr_ = make_rsrc(in_b + (int64_t)((BB) * g.C + (CH)) * g.iqs, plane_bytes); \
-        _Pragma("unroll") for (int m = 0; m < EH; ++m) DST[0][m] = buf_cplx<T>(rr_, r_lane, m * r_step); \
+        const __amdgpu_buffer_rsrc_t rr_ = make_rsrc(in_b + (int64_t)((BB) * g.C + (CH)) * g.iqs, ro.in_bytes); \
+        _Pragma("unroll") for (int m = 0; m < EH; ++m) DST[0][m] = buf_cplx<T>(rr_, r_off[m], m * r_step); \
     }
     cplx<T> cur[1][E], nxt[1][E];
-    DDS_LOAD_RHO(cur, 0, 0)
+    DDS_LOAD_RHO(cur, ro.b0, 0)
     constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
     cplx<T> twr[TWC];
     load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
@@ -212,7 +311,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
 
     T sv[6][E];
     if constexpr (!SL) DDS_LOAD_SPEC(sv, 0)
-    for (int b = 0; b < g.B; ++b) {
+    for (int b = ro.b0; b < ro.b1; ++b) {
         cplx<T> acc[6][1][E];
 #pragma unroll
         for (int v = 0; v < 6; ++v)
@@ -236,12 +335,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
                     // signs of mirrored spectrum rows (wave-uniform); staged
                     // values already carry the y sign
                     const int bit = ch * 6 + v;
-                    const T sy = (!SL && flip_y && ((g.sgn_y >> bit) & 1)) ? T(-1) : T(1);
-                    const T sz = ((g.sgn_z >> bit) & 1) ? -sy : sy;
+                    const bool ny = !SL && flip_y && ((g.sgn_y >> bit) & 1);
+                    const uint32_t my = sign_mask(ny);
+                    const uint32_t mz = zc ? sign_mask(ny != (((g.sgn_z >> bit) & 1) != 0)) : my;
 #pragma unroll
                     for (int m = 0; m < E; ++m) {
-                        const T sval = (SL && !(zc && 2 * m >= E)) ? sv[v][m]
-                                                                    : ((zc && 2 * m >= E) ? sz : sy) * sv[v][m];
+                        const T sval = (SL && 2 * m < E) ? sv[v][m] : flip_sign(sv[v][m], 2 * m >= E ? mz : my);
                         acc[v][0][m].x -= sval * cur[0][m].y;
                         acc[v][0][m].y += sval * cur[0][m].x;
                     }
@@ -253,7 +352,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
                 }
             }
         }
-        if (b + 1 < g.B) {      // first channel of the next realisation
+        if (b + 1 < ro.b1) {    // first channel of the next realisation
             DDS_LOAD_RHO(cur, b + 1, 0)
             if constexpr (!SL) DDS_LOAD_SPEC(sv, 0)
         }
@@ -263,13 +362,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             fft_regs_k<T, N, E, false, false, 1>(acc[v], twr, lds, 0, lay, c, j);
-            if (nq.own) {
-                cplx<T>* dst = out_b + (int64_t)(b * 6 + v) * g.oqs;
+            {
+                const __amdgpu_buffer_rsrc_t orr = make_rsrc(out_b + (int64_t)(b * 6 + v) * g.oqs, ro.out_bytes);
 #pragma unroll
-                for (int m = 0; m < EH; ++m) {
-                    const int z = j + Tc * m;
-                    if (z < g.nz) dst[z * ors] = acc[v][0][m];
-                }
+                for (int m = 0; m < EH; ++m) buf_store_cplx<T>(orr, o_off[m], m * o_step, acc[v][0][m]);
             }
             if (nq.mirror) {
                 cplx<T>* dst = mir_b + (int64_t)(b * 6 + v) * g.oqs;
@@ -286,7 +382,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
 
 // ----------------------------------------------------------------------------
 // Fused z pass, wave form (FP32, z length 64, 8 elements per thread). A block
-// owns TK = 8 consecutive kx columns at one ky, stages their spectrum tile in
+// owns TK = 8 consecutive kx columns at one ky (or a group of the Nyquist
+// strip, see z_roles), stages their spectrum tile in
 // LDS once (as the single-group form does) and runs WPB waves; wave w
 // evaluates realisations b = w, w + WPB, ... on its own. Its 64 lanes hold the
 // 8 columns with 8 lanes each (lane = 8 j + c: rows j + 8 m of column c), so
@@ -313,47 +410,44 @@ __global__ void __launch_bounds__(64 * WPB) k_z_wave(const cplx<T>* __restrict__
     constexpr bool HZ = true;              // the upper half of every input column is padding
     constexpr int KS = (6 * NC + 1) * TK;  // staged row stride (values)
     extern __shared__ unsigned char smem_raw[];
-    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    // the wave index is uniform over the wave: kept in a scalar register, the
+    // realisations (and the buffer resources of their planes) are too
+    const int lane = (int)threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int c = lane % TK, j = lane / TK;
-    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    int tile, ky;
-    z_block_coords(blk, g.ntiles, g.nky, tile, ky);
-    const int col = tile * TK + c;
-    const bool valid = col < g.ncols;
-    const int colc = valid ? col : 0;
-    const NyquistRole nq = nyquist_role(tile, TK, col, ky, valid, g);
+    const int blk = z_logical_block(g);
+    const ZRoles ro = z_roles<T>(blk, TK, c, g);
+    const NyquistRole nq = ro.nq;
     if (nq.skip_block) return;                   // uniform over the block, before any barrier
     const int ors = (int)g.ors;
     // spectrum tile (see the single-group form): rows kyc, mirrored rows signed
-    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
-    const int kyc = flip_y ? g.nky - ky : ky;
+    const bool flip_y = ro.flip_y;
     const bool zc = g.nkz_s < N;
     const int nkz = g.nkz_s;
-    const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * TK;
+    const T* sp = spec + ((int64_t)ro.kyc * g.ntiles + ro.tile) * (int64_t)g.C * 6 * nkz * TK;
     const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * TK * sizeof(T)));
     T* s_l = reinterpret_cast<T*>(smem_raw);
     const size_t stage_bytes = ((size_t)nkz * KS * sizeof(T) + 15) / 16 * 16;
     cplx<T>* xw = reinterpret_cast<cplx<T>*>(smem_raw + stage_bytes) + w * (N * TK);    // this wave's exchanges
     const ColMajor lay{TK};
-    // density rows z < nz; rows >= nz lie beyond the resource and read as zero;
-    // lanes of padding columns read the tile's first column
-    const cplx<T>* in_b = in + (int64_t)ky * g.ios + (int64_t)tile * TK;
-    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
-    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
+    // density rows z < nz (rows >= nz read zero; lanes without data read a
+    // valid column)
+    const cplx<T>* in_b = in + ro.in0;
+    int r_off[EH];
+    row_offsets<T, EH>(r_off, true, j, Tc, ro.lane_in, (int)g.irs, g.nz, ro.in_bytes);
     const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
-    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
-    cplx<T>* mir_b = out + (int64_t)(g.nky - ky) * g.oos + colc;
+    cplx<T>* out_b = out + ro.own;
+    cplx<T>* mir_b = out + ro.mir;
 
     cplx<T> nxt[NC][EH];
     auto load_rho = [&](int b) {
 #pragma unroll
         for (int ch = 0; ch < NC; ++ch) {
-            const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_b + (int64_t)(b * g.C + ch) * g.iqs, plane_bytes);
+            const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_b + (int64_t)(b * g.C + ch) * g.iqs, ro.in_bytes);
 #pragma unroll
-            for (int m = 0; m < EH; ++m) nxt[ch][m] = buf_cplx<T>(rr, r_lane, m * r_step);
+            for (int m = 0; m < EH; ++m) nxt[ch][m] = buf_cplx<T>(rr, r_off[m], m * r_step);
         }
     };
-    if (w < g.B) load_rho(w);
+    if (ro.b0 + w < ro.b1) load_rho(ro.b0 + w);
     constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
     cplx<T> twr[TWC];
     load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
@@ -370,7 +464,7 @@ __global__ void __launch_bounds__(64 * WPB) k_z_wave(const cplx<T>* __restrict__
     stage_spectrum_tile<T, NC, TK, 64 * WPB>(s_l, srs, nkz, flip_y, g.sgn_y, (int)threadIdx.x);
     __syncthreads();
 
-    for (int b = w; b < g.B; b += WPB) {
+    for (int b = ro.b0 + w; b < ro.b1; b += WPB) {
         cplx<T> rho[NC][1][E];
 #pragma unroll
         for (int ch = 0; ch < NC; ++ch) {
@@ -378,7 +472,7 @@ __global__ void __launch_bounds__(64 * WPB) k_z_wave(const cplx<T>* __restrict__
             for (int m = 0; m < EH; ++m) rho[ch][0][m] = nxt[ch][m];
             fft_regs_k<T, N, E, true, HZ, 1, TWC, true>(rho[ch], twr, xw, 0, lay, c, j);
         }
-        if (b + WPB < g.B) load_rho(b + WPB);
+        if (b + WPB < ro.b1) load_rho(b + WPB);
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             cplx<T> acc[1][E];
@@ -386,11 +480,11 @@ __global__ void __launch_bounds__(64 * WPB) k_z_wave(const cplx<T>* __restrict__
             for (int m = 0; m < E; ++m) acc[0][m] = {T(0), T(0)};
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch) {
-                const T sz = ((g.sgn_z >> (ch * 6 + v)) & 1) ? T(-1) : T(1);    // staged values carry the y sign
+                const uint32_t mz = sign_mask(zc && ((g.sgn_z >> (ch * 6 + v)) & 1));   // staged values carry the y sign
 #pragma unroll
                 for (int m = 0; m < E; ++m) {
                     const T sv = s_l[s_row[m] + (ch * 6 + v) * TK];
-                    const T sval = (zc && 2 * m >= E) ? sz * sv : sv;
+                    const T sval = 2 * m >= E ? flip_sign(sv, mz) : sv;
                     acc[0][m].x -= sval * rho[ch][0][m].y;
                     acc[0][m].y += sval * rho[ch][0][m].x;
                 }
@@ -418,7 +512,7 @@ __global__ void __launch_bounds__(64 * WPB) k_z_wave(const cplx<T>* __restrict__
 
 // ----------------------------------------------------------------------------
 // Fused z pass, grouped form. A block owns `tk` consecutive kx columns at one
-// ky and one group of Tc * tk threads per density channel (G = C groups). For
+// ky (or a group of the Nyquist strip, see z_roles) and one group of Tc * tk threads per density channel (G = C groups). For
 // every realisation b:
 //   1. group g transforms channel g along z (length N; rows z >= N/2 are the
 //      zero padding and are not loaded) and puts rho^_g(kz) in LDS;
@@ -456,36 +550,32 @@ __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ i
     const int t = threadIdx.x - grp * per;
     const int c = t % tk;
     const int j = t / tk;
-    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    int tile, ky;
-    z_block_coords(blk, g.ntiles, g.nky, tile, ky);
-    const int col = tile * tk + c;
-    const bool valid = col < g.ncols;
-    const int colc = valid ? col : 0;
+    const int blk = z_logical_block(g);
+    const ZRoles ro = z_roles<T>(blk, tk, c, g);
     const bool has_v = OPG * grp < 6;      // wave-uniform
     const ColMajor lay{ld};
     const int region = N * ld;             // one transform column block in LDS
 
-    // density rows z < nz of the block's columns; rows >= nz lie beyond the
-    // resource and read as zero. Lanes of padding columns (col >= ncols) read
-    // the tile's first column, which is valid.
-    const cplx<T>* in_g = in + (int64_t)ky * g.ios + (int64_t)tile * tk + (int64_t)grp * g.iqs;
+    // density rows z < nz of the block's columns (rows >= nz read zero; lanes
+    // without data read a valid column). A wave can hold two groups (tk Tc <
+    // 64), so the channel plane differs across its lanes: the loads take
+    // per-lane addresses rather than one buffer resource per wave.
+    const cplx<T>* in_l = in + ro.in0 + (int64_t)grp * g.iqs + ro.lane_in + (int64_t)j * g.irs;
     const int64_t in_real = (int64_t)g.C * g.iqs;
-    const uint32_t plane_bytes = (uint32_t)((size_t)g.nz * g.irs * sizeof(cplx<T>));
-    const int r_lane = (j * (int)g.irs + (valid ? c : 0)) * (int)sizeof(cplx<T>);
-    const int r_step = Tc * (int)g.irs * (int)sizeof(cplx<T>);
-    const int ors = (int)g.ors;                      // in-block offsets fit in 32 bits
-    cplx<T>* out_b = out + (int64_t)ky * g.oos + colc;
-    const NyquistRole nq = nyquist_role(tile, tk, col, ky, valid, g);
-    if (nq.skip_block) return;                   // uniform over the block, before any barrier
-    cplx<T>* mir_b = out + (int64_t)(g.nky - ky) * g.oos + colc;
-
+    const int64_t r_step = (int64_t)Tc * g.irs;
     cplx<T> fw[1][E];
-    {
-        const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_g, plane_bytes);
+    auto load_rows = [&](int b) {
 #pragma unroll
-        for (int m = 0; m < EH; ++m) fw[0][m] = buf_cplx<T>(rr, r_lane, m * r_step);
-    }
+        for (int m = 0; m < EH; ++m)
+            fw[0][m] = j + Tc * m < g.nz ? in_l[b * in_real + m * r_step] : cplx<T>{T(0), T(0)};
+    };
+    const int ors = (int)g.ors;                      // in-block offsets fit in 32 bits
+    cplx<T>* out_b = out + ro.own;
+    const NyquistRole nq = ro.nq;
+    if (nq.skip_block) return;                   // uniform over the block, before any barrier
+    cplx<T>* mir_b = out + ro.mir;
+
+    load_rows(ro.b0);
     constexpr int TWC = tw_count(N, E) > 0 ? tw_count(N, E) : 1;
     cplx<T> twr[TWC];
     load_tw_stages<T, N, E, 1, 0, TWC>(twr, j, tw + (N - 1));
@@ -495,13 +585,12 @@ __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ i
     // stands in for ky > Py/2; with a z mirror only kz <= N/2 is stored and
     // elements m >= E/2 read kz' = N - kz = (Tc - j) + Tc (E - 1 - m). Odd
     // planes change sign; the signs are applied once, here.
-    const bool flip_y = g.nky_s < g.nky && 2 * ky > g.nky;
-    const int kyc = flip_y ? g.nky - ky : ky;
+    const bool flip_y = ro.flip_y;
     const bool zc = g.nkz_s < N;
     const int nkz = g.nkz_s;
     T sv[OPG][NC][E];
     {
-        const T* sp = spec + ((int64_t)kyc * g.ntiles + tile) * (int64_t)g.C * 6 * nkz * tk;
+        const T* sp = spec + ((int64_t)ro.kyc * g.ntiles + ro.tile) * (int64_t)g.C * 6 * nkz * tk;
         const __amdgpu_buffer_rsrc_t srs = make_rsrc(sp, (uint32_t)((size_t)g.C * 6 * nkz * tk * sizeof(T)));
         const int s_lane = (j * tk + c) * (int)sizeof(T);
         const int s_lane_m = ((Tc - j) * tk + c) * (int)sizeof(T);
@@ -524,7 +613,7 @@ __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ i
             }
     }
 
-    for (int b = 0; b < g.B; ++b) {
+    for (int b = ro.b0; b < ro.b1; ++b) {
         // 1. forward transform of channel grp; its spectrum to LDS region grp
         fft_regs_k<T, N, E, true, HZ, 1, TWC, WV>(fw, twr, lds + grp * region, region, lay, c, j);
         __syncthreads();                             // the last stage's LDS reads are done
@@ -548,11 +637,7 @@ __global__ void __launch_bounds__(768) k_z_grouped(const cplx<T>* __restrict__ i
                     acc[k][m].y += sv[k][ch][m] * r.x;
                 }
             }
-        if (b + 1 < g.B) {
-            const __amdgpu_buffer_rsrc_t rr = make_rsrc(in_g + (b + 1) * in_real, plane_bytes);
-#pragma unroll
-            for (int m = 0; m < EH; ++m) fw[0][m] = buf_cplx<T>(rr, r_lane, m * r_step);
-        }
+        if (b + 1 < ro.b1) load_rows(b + 1);
         // inverse transforms (their first stage's barrier precedes any LDS write;
         // wave-local stages have none, so the block meets here first)
         if constexpr (WV) __syncthreads();

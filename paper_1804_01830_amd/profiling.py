@@ -86,7 +86,12 @@ def _z_shape(line):
         b = cfg["batch"]
         threads = 64 * (4 if b >= 4 else (2 if b >= 2 else 1))
     m1 = info["padded"][0] // 2 + 1
-    blocks = ((m1 + tk - 1) // tk) * info["padded"][1]
+    py = info["padded"][1]
+    tiles = (m1 + tk - 1) // tk
+    if m1 > tk and (m1 - 1) % tk == 0:            # the Nyquist strip: column M at tk ky, one realisation a block
+        blocks = (tiles - 1) * py + (py // 2 + tk) // tk * cfg["batch"]
+    else:
+        blocks = tiles * py
     return threads, blocks * threads
 
 

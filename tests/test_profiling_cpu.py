@@ -15,7 +15,7 @@ LINE = {"metric": "m", "config": {"grid": [128, 128, 32], "workload": "disk-mixe
         "plan_info": {"padded": [256, 256, 64], "tile_z": 8, "ez": 4, "z_groups": 1},
         "roofline": {"kernel": "k_z_serial", "algorithmic_bytes_per_launch": 1000000}}
 BLOCK = 8 * 16                                    # tk * Pz / E threads
-GRID = ((129 + 7) // 8) * 256 * BLOCK             # kx tiles x ky rows blocks
+GRID = (128 // 8 * 256 + (128 + 8) // 8 * 8) * BLOCK   # kx tiles x ky rows, Nyquist strip groups x batch
 
 
 def _write(directory, counter, rows):
