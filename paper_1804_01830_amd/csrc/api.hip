@@ -45,6 +45,7 @@ struct Shape {
     bool mir_y, mir_z;          // spectrum kept for ky <= Py/2 (kz <= Pz/2) only, by mirror parity
     int nkys, nkzs;             // spectrum rows kept along ky and kz
     uint64_t sgn_y, sgn_z;      // bit c*6+v: S_{v,c} odd under ky -> -ky (kz -> -kz)
+    bool zstrip;                // the spectrum keeps the fused z pass's Nyquist strip (z_nyq_groups)
     int64_t cells() const { return (int64_t)N[0] * N[1] * N[2]; }
     int64_t padded() const { return (int64_t)P[0] * P[1] * P[2]; }
 };
@@ -114,6 +115,9 @@ Shape make_shape(const ddstress_desc* d) {
     s.B = d->batch;
     s.elem = d->precision == 32 ? 4 : 8;
     s.zg = default_z_groups(s.P[2], s.C, s.B, s.elem);
+    // A strip block carries one realisation with one cache line per value;
+    // with few realisations it would outlast the other blocks of the launch.
+    s.zstrip = s.B >= kZStripBatch;
     s.tkz = default_z_tk(s.P[2], s.C, s.zg, s.elem);
     s.ntz = (s.M1 + s.tkz - 1) / s.tkz;
     set_mirrors(s, predict_mirror(d, 1), predict_mirror(d, 2));
@@ -330,7 +334,7 @@ void build_spectrum(ddstress_plan_s* p, hipStream_t st) {
         launch_col_fft<double>(s.P[2], default_ev_col(s.P[2]), true, kc.as<cplx<double>>(), kc.as<cplx<double>>(),
                                gz, tw, tkz, st);
         launch_extract<T>(kc.as<cplx<double>>(), p->spec->as<T>(), l, s.C, s.M1, s.wx, s.P[1], s.P[2], s.nkys, s.nkzs,
-                          s.tkz, s.ntz, inv_p, maxbits.as<unsigned long long>(), st);
+                          s.tkz, s.ntz, s.zstrip, inv_p, maxbits.as<unsigned long long>(), st);
     }
     unsigned long long bits[2] = {0, 0};
     check_hip(hipMemcpyAsync(bits, maxbits.p, sizeof(bits), hipMemcpyDeviceToHost, st), "spectrum check readback");
@@ -434,6 +438,7 @@ ZGeom z_geom(const Shape& s, int tk, int nb, bool kin, bool kout) {
     g.ors = kout ? s.wx : (int64_t)Py * s.wx;
     g.oos = kout ? (int64_t)Nz * s.wx : s.wx;
     g.oqs = g.iqs;
+    g.strip = s.zstrip ? 1 : 0;
     return g;
 }
 
@@ -927,6 +932,7 @@ ddstress_status ddstress_plan_share(ddstress_plan src, int32_t batch, ddstress_p
             p->shape.nkzs = src->shape.nkzs;
             p->shape.sgn_y = src->shape.sgn_y;
             p->shape.sgn_z = src->shape.sgn_z;
+            p->shape.zstrip = src->shape.zstrip;
             p->spec = src->spec;
             p->tw = src->tw;
             p->rows_x = src->rows_x;

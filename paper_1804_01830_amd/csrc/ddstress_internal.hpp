@@ -157,10 +157,14 @@ struct ZGeom {
     int C, B;              // channels and batch
     int64_t irs, iqs, ios; // input z / plane / ky strides
     int64_t ors, oqs, oos; // output strides (6B planes)
+    int strip;             // the spectrum keeps the Nyquist strip where the tiles allow it
     int nyq;               // groups of the Nyquist strip (z_nyq_groups; set by launch_z_fused)
 };
+// Plans of at least this many realisations keep the Nyquist strip.
+constexpr int kZStripBatch = 4;
 
-// Nyquist strip of the fused z pass. When the last kx tile would hold the
+// Nyquist strip of the fused z pass (plans of kZStripBatch or more
+// realisations, ZGeom::strip). When the last kx tile would hold the
 // column kx = M (= ncols - 1) alone, which happens whenever M is a multiple of
 // the tile width tk, that tile's blocks hold the column at tk consecutive ky
 // instead: group q covers ky = q tk .. q tk + tk - 1, and only ky <= Py/2 is
@@ -250,7 +254,7 @@ void launch_mirror_stats(const double* kr, const int P[3], unsigned long long* s
 // kyc < nky, kzc < nkz.
 template <typename T>
 void launch_extract(const cplx<double>* kh, T* spec, int line, int C, int ncols, int64_t wx, int Py, int Pz,
-                    int nky, int nkz, int tk, int ntiles, double inv_p, unsigned long long* maxbits,
+                    int nky, int nkz, int tk, int ntiles, bool strip, double inv_p, unsigned long long* maxbits,
                     hipStream_t s);
 
 }  // namespace dds

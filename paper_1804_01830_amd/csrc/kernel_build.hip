@@ -220,14 +220,14 @@ __global__ void __launch_bounds__(256) k_mirror_stats(const double* __restrict__
 // Spectrum extraction: S = Im(K^) / P for the channels 3*line .. 3*line+2,
 // stored as [kyc][tile][c][v][kzc][tk] for kyc < nky, kzc < nkz (the kept
 // halves when a mirror symmetry lets the rest be reconstructed). With a
-// Nyquist strip (z_nyq_groups) the last tile's slot at row q holds instead
+// Nyquist strip (strip_on and z_nyq_groups) the last tile's slot at row q holds instead
 // the column kx = M at ky = q tk + col, for ky <= Py/2 (zeros elsewhere). One
 // thread per (kx in the tiled range, kyc, kzc), looping over the 18 planes;
 // also the maxima of |Re K^| and |Im K^| over the kept entries.
 template <typename T>
 __global__ void __launch_bounds__(256) k_extract(const cplx<double>* __restrict__ kh, T* __restrict__ spec,
                                                  int line, int C, int ncols, int64_t wx, int Py, int Pz, int nky,
-                                                 int nkz, int tk, int ntiles, double inv_p,
+                                                 int nkz, int tk, int ntiles, int strip_on, double inv_p,
                                                  unsigned long long* __restrict__ maxbits) {
     const int kx = blockIdx.x * blockDim.x + threadIdx.x;
     const int ky = blockIdx.y;
@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(256) k_extract(const cplx<double>* __restrict_
     double re = 0.0, im = 0.0;
     if (kx < kxr) {
         const int tile = kx / tk, col = kx % tk;
-        const bool strip = tile == ntiles - 1 && z_nyq_groups(ncols, tk, Py) > 0;
+        const bool strip = strip_on && tile == ntiles - 1 && z_nyq_groups(ncols, tk, Py) > 0;
         const int sx = strip ? ncols - 1 : kx;                  // source column and row
         const int sy = strip ? ky * tk + col : ky;
         const bool have = strip ? 2 * sy <= Py : kx < ncols;
@@ -326,19 +326,19 @@ void launch_mirror_stats(const double* kr, const int P[3], unsigned long long* s
 
 template <typename T>
 void launch_extract(const cplx<double>* kh, T* spec, int line, int C, int ncols, int64_t wx, int Py, int Pz,
-                    int nky, int nkz, int tk, int ntiles, double inv_p, unsigned long long* maxbits,
+                    int nky, int nkz, int tk, int ntiles, bool strip, double inv_p, unsigned long long* maxbits,
                     hipStream_t s) {
     const int kxr = ntiles * tk;
     const dim3 grid((unsigned)((kxr + 255) / 256), (unsigned)nky, (unsigned)nkz);
     hipLaunchKernelGGL((k_extract<T>), grid, dim3(256), 0, s, kh, spec, line, C, ncols, wx, Py, Pz, nky, nkz, tk,
-                       ntiles, inv_p, maxbits);
+                       ntiles, strip ? 1 : 0, inv_p, maxbits);
     check_hip(hipGetLastError(), "spectrum extraction launch");
 }
 
 template void launch_extract<float>(const cplx<double>*, float*, int, int, int, int64_t, int, int, int, int, int,
-                                    int, double, unsigned long long*, hipStream_t);
+                                    int, bool, double, unsigned long long*, hipStream_t);
 template void launch_extract<double>(const cplx<double>*, double*, int, int, int, int64_t, int, int, int, int, int,
-                                     int, double, unsigned long long*, hipStream_t);
+                                     int, bool, double, unsigned long long*, hipStream_t);
 
 template <typename T>
 void fill_twiddles(cplx<T>* host) {

@@ -509,7 +509,7 @@ void launch_z_fused(int N, int ev, int groups, const cplx<T>* in, cplx<T>* out, 
     if (tk < 1 || geom.ntiles != (geom.ncols + tk - 1) / tk)
         fail(DDSTRESS_E_INVALID, "fused z tiles do not match the tile width");
     ZGeom g = geom;
-    g.nyq = z_nyq_groups(g.ncols, tk, g.nky);
+    g.nyq = g.strip ? z_nyq_groups(g.ncols, tk, g.nky) : 0;
     // tiles x ky rows; in place of the Nyquist strip's tile, its groups x realisations
     const int64_t blocks = g.nyq > 0 ? (int64_t)(g.ntiles - 1) * g.nky + (int64_t)g.nyq * g.B
                                      : (int64_t)g.ntiles * g.nky;

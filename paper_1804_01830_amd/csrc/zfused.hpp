@@ -335,14 +335,22 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
                     // signs of mirrored spectrum rows (wave-uniform); staged
                     // values already carry the y sign
                     const int bit = ch * 6 + v;
-                    const bool ny = !SL && flip_y && ((g.sgn_y >> bit) & 1);
-                    const uint32_t my = sign_mask(ny);
-                    const uint32_t mz = zc ? sign_mask(ny != (((g.sgn_z >> bit) & 1) != 0)) : my;
+                    T sval[E];
+                    if constexpr (SL) {
+                        // staged values carry the y sign: the z sign of the upper elements
+                        const uint32_t mz = sign_mask(zc && ((g.sgn_z >> bit) & 1));
+#pragma unroll
+                        for (int m = 0; m < E; ++m) sval[m] = 2 * m < E ? sv[v][m] : flip_sign(sv[v][m], mz);
+                    } else {
+                        const T sy = (flip_y && ((g.sgn_y >> bit) & 1)) ? T(-1) : T(1);
+                        const T sz = ((g.sgn_z >> bit) & 1) ? -sy : sy;
+#pragma unroll
+                        for (int m = 0; m < E; ++m) sval[m] = ((zc && 2 * m >= E) ? sz : sy) * sv[v][m];
+                    }
 #pragma unroll
                     for (int m = 0; m < E; ++m) {
-                        const T sval = (SL && 2 * m < E) ? sv[v][m] : flip_sign(sv[v][m], 2 * m >= E ? mz : my);
-                        acc[v][0][m].x -= sval * cur[0][m].y;
-                        acc[v][0][m].y += sval * cur[0][m].x;
+                        acc[v][0][m].x -= sval[m] * cur[0][m].y;
+                        acc[v][0][m].y += sval[m] * cur[0][m].x;
                     }
                 }
                 if (more) {
@@ -362,10 +370,18 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(TK > 0
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
             fft_regs_k<T, N, E, false, false, 1>(acc[v], twr, lds, 0, lay, c, j);
-            {
+            if constexpr (SL) {
                 const __amdgpu_buffer_rsrc_t orr = make_rsrc(out_b + (int64_t)(b * 6 + v) * g.oqs, ro.out_bytes);
 #pragma unroll
                 for (int m = 0; m < EH; ++m) buf_store_cplx<T>(orr, o_off[m], m * o_step, acc[v][0][m]);
+            } else if (nq.own) {
+                // (the unstaged form is short of scalar registers: plain stores)
+                cplx<T>* dst = out + ro.own + (int64_t)(b * 6 + v) * g.oqs;
+#pragma unroll
+                for (int m = 0; m < EH; ++m) {
+                    const int z = j + Tc * m;
+                    if (z < g.nz) dst[z * ors] = acc[v][0][m];
+                }
             }
             if (nq.mirror) {
                 cplx<T>* dst = mir_b + (int64_t)(b * 6 + v) * g.oqs;

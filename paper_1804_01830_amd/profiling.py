@@ -88,7 +88,7 @@ def _z_shape(line):
     m1 = info["padded"][0] // 2 + 1
     py = info["padded"][1]
     tiles = (m1 + tk - 1) // tk
-    if m1 > tk and (m1 - 1) % tk == 0:            # the Nyquist strip: column M at tk ky, one realisation a block
+    if cfg["batch"] >= 4 and m1 > tk and (m1 - 1) % tk == 0:   # the Nyquist strip (plans of 4 or more)
         blocks = (tiles - 1) * py + (py // 2 + tk) // tk * cfg["batch"]
     else:
         blocks = tiles * py
