@@ -39,3 +39,25 @@ def rel_l2(got, ref):
         r = np.take(ref, v, axis=-4 if ref.ndim >= 4 else 0)
         comp.append(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-3 * whole))
     return np.array(comp), np.linalg.norm(got - ref) / whole
+
+
+def rel_l2_split(got, ref, floor=1e-3):
+    """The per-component errors of rel_l2, split by how they are measured:
+    `own` maps each component whose reference norm is at least `floor` of the
+    whole-tensor norm to its error relative to its own norm; `small` maps the
+    others (components that are zero or nearly so, where a relative error has
+    no meaning) to their error norm relative to the whole-tensor norm."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    whole = np.linalg.norm(ref)
+    own, small = {}, {}
+    for v in range(6):
+        g = np.take(got, v, axis=-4 if got.ndim >= 4 else 0)
+        r = np.take(ref, v, axis=-4 if ref.ndim >= 4 else 0)
+        rn, e = np.linalg.norm(r), np.linalg.norm(g - r)
+        if whole > 0.0 and rn >= floor * whole:
+            own[v] = e / rn
+        else:
+            small[v] = e / whole if whole > 0.0 else (0.0 if e == 0.0 else np.inf)
+    return own, small
+

@@ -10,7 +10,7 @@ import sys
 import numpy as np
 import pytest
 
-from gpu_util import gpu_stress, rel_l2
+from gpu_util import gpu_stress, rel_l2, rel_l2_split
 from oracle import stress_direct, interaction_kernel, KernelGeometry
 from paper_1804_01830_amd import workloads as W
 
@@ -60,8 +60,13 @@ def test_full_field_parity(name, precision):
     _say(f"[parity] {name} precision={precision} n={w['n']} B={w['rho'].shape[0]}")
     got = gpu_stress(w, precision)
     comp, whole = rel_l2(got, ref)
+    own, small = rel_l2_split(got, ref)
     _say(f"  rel L2 per component {np.array2string(comp, precision=2)} whole {whole:.2e}")
+    _say("  against their own norm: " + ", ".join(f"{v}: {e:.2e}" for v, e in own.items())
+         + ("; small components against the whole norm: " + ", ".join(f"{v}: {e:.2e}" for v, e in small.items())
+            if small else ""))
     assert np.all(comp <= TOL[precision]) and whole <= TOL[precision]
+    assert all(e <= TOL[precision] for e in own.values()) and all(e <= TOL[precision] for e in small.values())
 
 
 def test_zero_density_gives_exact_zero():
